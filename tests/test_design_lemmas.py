@@ -1,0 +1,193 @@
+"""CPU checks of the two facts the GPU kernels rest on, against the oracle.
+
+1. Locality.  The greedy first error equals the smallest position i at which
+   a predicate C(i) over the window b[i-3..i+3] holds:
+     * b_i not a continuation: the character announced at i breaks a rule
+       of Section 3 (bytes past the end count as missing);
+     * b_i a continuation: no j in {i-1, i-2, i-3} has b_j >= 0xC0
+       announcing more than i-j bytes with only continuations in between.
+   For UTF-16: a high word not followed by a low word, or a low word not
+   preceded by a high word.
+2. Detection.  Let must(t) = [b_{t-1} >= C0] | [b_{t-2} >= E0] |
+   [b_{t-3} >= F0] and cont(t) = [b_t in 80..BF].  For the first error e,
+   either must(t) != cont(t) for some t in [e, e+3] (bytes past the end
+   read as 0x00), or the character at e is structurally complete and its
+   decoded value breaks rule 4, 5 or 6 (or its lead breaks rule 1).  The
+   kernels therefore only run the exact per-position scan on waves where
+   one of those cheap signals fired.
+3. Per-wave control.  A wave owning positions [a, z) computes its byte
+   class over [a-3, z) (the three bytes before it included); with no byte
+   >= 0xF0 it drops the F0 term of must(), with no byte >= 0xE0 also the E0
+   term, and with no byte >= 0x80 it raises nothing.  It flags when a
+   mismatch occurs at one of its positions or a value rule fails at one of
+   its leading bytes, and a flagged wave evaluates C exactly over
+   [a-3, z).  Splitting a buffer into waves at any point, the smallest C
+   found this way is the greedy first error.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ALPHA = [0x41, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC2, 0xDF, 0xE0, 0xE1, 0xED, 0xEF,
+         0xF0, 0xF4, 0xF5, 0xF8]
+
+
+def is_cont(x):
+    return 0x80 <= x <= 0xBF
+
+
+def announced(x):
+    return 1 if x < 0x80 else 2 if x < 0xE0 else 3 if x < 0xF0 else 4
+
+
+def char_fails(b, i):
+    """Rules 1-6 for the character announced at a non-continuation b[i]."""
+    x = b[i]
+    if x < 0x80:
+        return False
+    if x >= 0xF8:
+        return True
+    L = announced(x)
+    for k in range(1, L):
+        if i + k >= len(b) or not is_cont(b[i + k]):
+            return True
+    cp = x & (0x7F >> L)
+    for k in range(1, L):
+        cp = (cp << 6) | (b[i + k] & 0x3F)
+    lo = {2: 0x80, 3: 0x800, 4: 0x10000}[L]
+    return cp < lo or cp > 0x10FFFF or 0xD800 <= cp <= 0xDFFF
+
+
+def C(b, i):
+    if not is_cont(b[i]):
+        return char_fails(b, i)
+    for d in (1, 2, 3):
+        j = i - d
+        if j < 0:
+            break
+        if b[j] >= 0xC0 and announced(b[j]) > d and all(is_cont(b[t]) for t in range(j + 1, i)):
+            return False
+    return True
+
+
+def byte_at(b, t):
+    return b[t] if 0 <= t < len(b) else 0x00
+
+
+def must(b, t, terms=3):
+    m = byte_at(b, t - 1) >= 0xC0
+    if terms >= 2:
+        m = m or byte_at(b, t - 2) >= 0xE0
+    if terms >= 3:
+        m = m or byte_at(b, t - 3) >= 0xF0
+    return m
+
+
+def range_flag(b, i):
+    """Value rules (and rule 1) at a non-continuation byte whose announced
+    continuation bytes are all present."""
+    x = b[i]
+    if x < 0x80 or is_cont(x):
+        return False
+    if x >= 0xF8:
+        return True
+    L = announced(x)
+    if any(not is_cont(byte_at(b, i + k)) for k in range(1, L)) or i + L > len(b):
+        return False
+    return char_fails(b, i)
+
+
+def check_buffer(b):
+    st, e = O.validate_utf8(np.array(b, dtype=np.uint8))
+    cs = [i for i in range(len(b)) if C(b, i)]
+    if st == 0:
+        assert not cs, bytes(b).hex()
+        return
+    assert cs and cs[0] == e, (bytes(b).hex(), cs, e)
+    # detection
+    mis = any(must(b, t) != is_cont(byte_at(b, t)) for t in range(e, e + 4))
+    assert mis or range_flag(b, e), bytes(b).hex()
+    # narrowed detectors when no byte >= F0 (or >= E0) occurs at or after e's window
+    for terms, bound in ((2, 0xF0), (1, 0xE0)):
+        if all(x < bound for x in b):
+            mis = any(must(b, t, terms) != is_cont(byte_at(b, t)) for t in range(e, e + 4))
+            assert mis or range_flag(b, e), (terms, bytes(b).hex())
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_locality_and_detection_exhaustive(n):
+    for b in itertools.product(ALPHA, repeat=n):
+        check_buffer(list(b))
+
+
+def test_locality_and_detection_random_long():
+    rng = np.random.default_rng(5)
+    alpha = np.array(ALPHA + [0x20, 0x7F, 0xBE, 0xE4, 0xB8, 0xF1, 0xF3], dtype=np.uint8)
+    for _ in range(40000):
+        n = int(rng.integers(5, 12))
+        check_buffer(alpha[rng.integers(0, alpha.size, size=n)].tolist())
+
+
+def test_utf16_locality_exhaustive():
+    W = [0x0041, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0xE000]
+    for n in range(1, 6):
+        for w in itertools.product(W, repeat=n):
+            st, e = O.validate_utf16le(np.array(w, dtype=np.uint16))
+            hi = [0xD800 <= x <= 0xDBFF for x in w]
+            lo = [0xDC00 <= x <= 0xDFFF for x in w]
+            cs = [i for i in range(n)
+                  if (hi[i] and (i + 1 >= n or not lo[i + 1])) or (lo[i] and (i == 0 or not hi[i - 1]))]
+            if st == 0:
+                assert not cs
+            else:
+                assert cs[0] == e
+
+
+def wave_class(b, lo, hi):
+    seg = [b[t] for t in range(max(lo, 0), min(hi, len(b)))]
+    top = max(seg) if seg else 0
+    return 0 if top < 0x80 else 1 if top < 0xE0 else 2 if top < 0xF0 else 3
+
+
+def wave_found(b, a, z):
+    """Model of one wave: returns the exact C positions it reports, or []."""
+    n = len(b)
+    cls = wave_class(b, a - 3, z)
+    if cls == 0:
+        return []
+    terms = cls
+    flag = any(must(b, t, terms) != is_cont(byte_at(b, t)) for t in range(a, z))
+    flag = flag or any(range_flag(b, i) for i in range(max(a, 0), min(z, n)))
+    if not flag:
+        return []
+    return [i for i in range(max(a - 3, 0), min(z, n)) if C(b, i)]
+
+
+def check_split(b):
+    n = len(b)
+    st, e = O.validate_utf8(np.array(b, dtype=np.uint8))
+    for cut in range(0, n + 1):
+        waves = [(0, cut), (cut, n + 3)] if cut > 0 else [(0, n + 3)]
+        found = [i for a, z in waves for i in wave_found(b, a, z)]
+        if st == 0:
+            assert not found, bytes(b).hex()
+        else:
+            assert found and min(found) == e, (bytes(b).hex(), cut, found, e)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_wave_control_exhaustive(n):
+    alpha = [0x41, 0x80, 0x9F, 0xA0, 0xBF, 0xC0, 0xC2, 0xE0, 0xE4, 0xED, 0xF0, 0xF4, 0xF5, 0xF8]
+    for b in itertools.product(alpha, repeat=n):
+        check_split(list(b))
+
+
+def test_wave_control_random_long():
+    rng = np.random.default_rng(6)
+    alpha = np.array(ALPHA + [0x20, 0x7F, 0xBE, 0xE4, 0xB8, 0xF1, 0xF3], dtype=np.uint8)
+    for _ in range(6000):
+        n = int(rng.integers(5, 14))
+        check_split(alpha[rng.integers(0, alpha.size, size=n)].tolist())
