@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Benchmark: validating UTF-8 <-> UTF-16LE transcoding on one MI355X.
+
+One step converts, with validation, every buffer of the 1 GiB script-mix
+workload in both directions:
+
+* UTF-8 -> UTF-16LE: five 1 GiB UTF-8 buffers (ASCII, Latin, Cyrillic, CJK,
+  emoji mixes) and their invalid variants (errors injected at a rate of
+  1e-6 per byte);
+* UTF-16LE -> UTF-8: five 1 GiB UTF-16LE buffers of the same mixes and their
+  invalid variants (unpaired surrogates at a rate of 1e-6 per word).
+
+Inputs and outputs are resident in HBM before timing starts; each step
+enqueues the 20 conversions (asynchronous C-ABI calls) and copies their 20
+results back to the host.  ``value`` is input bytes per second over the
+timed steps.  Per-launch HIP events give every kernel's duration; the
+roofline entry is the dominant kernel's algorithmic bytes (input read +
+output written) per second against the 8 TB/s HBM peak.  The length and
+validate-only kernels, the 1 MiB single-buffer latency and the CPU oracle
+(on a bounded sample of the same buffers, one core) are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib S]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import statistics
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workloads import (SCRIPT_MIXES, SEED_MIX1M, SEED_UTF8, SEED_UTF8_INVALID, SEED_UTF16,  # noqa: E402
+                       SEED_UTF16_INVALID, make_buffer)
+
+METRIC = "input GB/s validated+transcoded (UTF-8<->UTF-16LE) and % of HBM roofline, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+ERROR_RATE = 1e-6
+KERNEL_SOURCES = ["paper_2111_08692_amd/csrc/device_common.hpp", "paper_2111_08692_amd/csrc/utf8_kernels.hip",
+                  "paper_2111_08692_amd/csrc/utf16_kernels.hip"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# inputs
+# ---------------------------------------------------------------------------
+
+def generate(size: int):
+    """All buffers of the workload (host numpy), generated before any GPU
+    work so the generator can fork worker processes."""
+    ex = ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("fork"))
+    bufs = []
+    t0 = time.time()
+    for mix in SCRIPT_MIXES:
+        for enc, seed, eseed in (("utf-8", SEED_UTF8[mix], SEED_UTF8_INVALID[mix]),
+                                 ("utf-16-le", SEED_UTF16[mix], SEED_UTF16_INVALID[mix])):
+            valid = make_buffer(mix, size, seed, encoding=enc, executor=ex)
+            bad = make_buffer(mix, size, seed, encoding=enc, error_rate=ERROR_RATE, error_seed=eseed, executor=ex)
+            bufs.append((mix, enc, "valid", valid))
+            bufs.append((mix, enc, "invalid", bad))
+            log(f"generated {mix} {enc} ({time.time() - t0:.1f}s)")
+    small = make_buffer("mix1m", 1 << 20, SEED_MIX1M)
+    ex.shutdown()
+    return bufs, small
+
+
+def cut_utf8(a: np.ndarray, n: int) -> np.ndarray:
+    n = min(n, a.size)
+    while 0 < n < a.size and (a[n] & 0xC0) == 0x80:
+        n -= 1
+    return a[:n]
+
+
+def cut_utf16(a: np.ndarray, m: int) -> np.ndarray:
+    m = min(m, a.size)
+    if 0 < m < a.size and 0xD800 <= a[m - 1] <= 0xDBFF:
+        m -= 1
+    return a[:m]
+
+
+def cpu_baseline(bufs, sample_bytes: int):
+    """The oracle, single-threaded, on the first ``sample_bytes`` of every
+    valid buffer, both directions."""
+    import oracle
+    oracle.build(force=False)
+    total_in = 0
+    total_t = 0.0
+    for mix, enc, kind, b in bufs:
+        if kind != "valid":
+            continue
+        if enc == "utf-8":
+            s = cut_utf8(b.data, sample_bytes)
+            t = time.perf_counter()
+            st, cnt, _ = oracle.convert_utf8_to_utf16le(s)
+            total_t += time.perf_counter() - t
+            total_in += s.size
+        else:
+            s = cut_utf16(b.data, sample_bytes // 2)
+            t = time.perf_counter()
+            st, cnt, _ = oracle.convert_utf16le_to_utf8(s)
+            total_t += time.perf_counter() - t
+            total_in += 2 * s.size
+        assert st == 0, (mix, enc, st)
+    return {"value": round(total_in / total_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_bytes >> 20} MiB of each of the 10 valid buffers (5 mixes x 2 directions), "
+                      f"{total_in / 2**30:.2f} GiB input, {total_t:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+# main
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size-mib", type=int, default=1024, help="bytes per buffer (MiB); the workload is 1024")
+    ap.add_argument("--cpu-sample-mib", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported "
+                                   "(the transcoder is a single-GPU path, see DESIGN.md for how it would shard)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    size = args.size_mib << 20
+    bufs, small = generate(size)
+
+    import torch
+    import paper_2111_08692_amd as G
+
+    assert torch.cuda.is_available(), "no GPU"
+    G.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # device-resident inputs
+    dbufs = []
+    for mix, enc, kind, b in bufs:
+        host = torch.from_numpy(b.data.view(np.uint8) if enc == "utf-8" else b.data.view(np.int16))
+        dbufs.append(host.to(dev))
+    torch.cuda.synchronize()
+    out16 = torch.empty(size, dtype=torch.int16, device=dev)          # >= n words for 8->16
+    out8 = torch.empty(3 * (size // 2), dtype=torch.uint8, device=dev)  # >= 3m bytes for 16->8
+    res = torch.zeros((len(bufs), 2), dtype=torch.int64, device=dev)
+    lens = torch.zeros(len(bufs), dtype=torch.int64, device=dev)
+
+    # output sizes (length queries) for the algorithmic byte counts
+    for i, ((mix, enc, kind, b), d) in enumerate(zip(bufs, dbufs)):
+        if enc == "utf-8":
+            G.utf16_length_from_utf8_async(d, lens[i])
+        else:
+            G.utf8_length_from_utf16le_async(d, lens[i])
+    out_units = lens.cpu().tolist()
+
+    def enqueue(i, d, enc):
+        if enc == "utf-8":
+            rc = G.convert_utf8_to_utf16le_async(d, out16, res[i])
+        else:
+            rc = G.convert_utf16le_to_utf8_async(d, out8, res[i])
+        assert rc == 0, rc
+
+    def step(events=None):
+        for i, ((mix, enc, kind, b), d) in enumerate(zip(bufs, dbufs)):
+            if events is not None:
+                events[i][0].record(stream)
+            enqueue(i, d, enc)
+            if events is not None:
+                events[i][1].record(stream)
+        return res.cpu()
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    all_events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in bufs] for _ in range(args.steps)]
+    log("timed steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step(all_events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # results must match what the generator knows
+    results = r.tolist()
+    for (mix, enc, kind, b), (st, cnt), units in zip(bufs, results, out_units):
+        st &= 0xFFFFFFFF
+        if kind == "valid":
+            assert st == 0 and cnt == units, (mix, enc, st, cnt, units)
+        else:
+            assert st in ((1, 2, 3, 4, 5, 6) if enc == "utf-8" else (7, 8)) and cnt == b.first_error, \
+                (mix, enc, st, cnt, b.first_error)
+
+    in_bytes = sum(int(b.data.nbytes) for _, _, _, b in bufs)
+    value = in_bytes * args.steps / elapsed / 1e9
+
+    # per-launch kernel durations
+    dur = np.array([[s.elapsed_time(e) for s, e in row] for row in all_events]) / 1e3   # seconds
+    per = {}
+    kern_time = {"utf8_tile_kernel<convert>": 0.0, "utf16_tile_kernel<convert>": 0.0}
+    kern_bytes = {"utf8_tile_kernel<convert>": 0, "utf16_tile_kernel<convert>": 0}
+    for i, (mix, enc, kind, b) in enumerate(bufs):
+        t = float(np.median(dur[:, i]))
+        nin = int(b.data.nbytes)
+        alg = nin + (2 * out_units[i] if enc == "utf-8" else out_units[i])
+        name = "utf8_tile_kernel<convert>" if enc == "utf-8" else "utf16_tile_kernel<convert>"
+        kern_time[name] += float(dur[:, i].sum())
+        kern_bytes[name] += alg * args.steps
+        key = f"{mix}/{'8to16' if enc == 'utf-8' else '16to8'}/{kind}"
+        per[key] = {"input_GBps": round(nin / t / 1e9, 1), "hbm_GBps": round(alg / t / 1e9, 1),
+                    "roofline_frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 3), "ms": round(t * 1e3, 4)}
+    dom = max(kern_time, key=kern_time.get)
+    achieved = kern_bytes[dom] / kern_time[dom] / 1e9
+    launches = args.steps * sum(1 for _, enc, _, _ in bufs if (enc == "utf-8") == dom.startswith("utf8"))
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and dom in tr.get("kernels", {}):
+            traffic = tr["kernels"][dom]
+
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "launches": launches,
+                "algorithmic_bytes_per_launch": int(kern_bytes[dom] / launches),
+                "avg_launch_ms": round(kern_time[dom] / launches * 1e3, 4)}
+
+    # auxiliary kernels: validate-only and length-only on the valid buffers
+    aux = {}
+    for name, fn in (("validate", None), ("length", None)):
+        tt, nb = 0.0, 0
+        for i, ((mix, enc, kind, b), d) in enumerate(zip(bufs, dbufs)):
+            if kind != "valid":
+                continue
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+            for s_, e_ in ev:
+                s_.record(stream)
+                if name == "validate":
+                    (G.validate_utf8_async if enc == "utf-8" else G.validate_utf16le_async)(d, res[i])
+                else:
+                    (G.utf16_length_from_utf8_async if enc == "utf-8" else G.utf8_length_from_utf16le_async)(
+                        d, lens[i])
+                e_.record(stream)
+            torch.cuda.synchronize()
+            tt += statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
+            nb += int(b.data.nbytes)
+        aux[f"{name}_only_input_GBps"] = round(nb / tt / 1e9, 1)
+        aux[f"{name}_only_roofline_frac"] = round(nb / tt / 1e9 / HBM_PEAK_GBS, 3)
+
+    # the 1 MiB single buffer: latency of one synchronous call
+    ds = torch.from_numpy(small.data).to(dev)
+    o16 = torch.empty(small.data.size, dtype=torch.int16, device=dev)
+    for _ in range(20):
+        G.convert_utf8_to_utf16le(ds, out=o16)
+    lat = []
+    for _ in range(200):
+        t = time.perf_counter()
+        st, cnt, _ = G.convert_utf8_to_utf16le(ds, out=o16)
+        lat.append(time.perf_counter() - t)
+    assert st == 0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for s_, e_ in ev:
+        s_.record(stream)
+        G.convert_utf8_to_utf16le_async(ds, o16, res[0])
+        e_.record(stream)
+    torch.cuda.synchronize()
+    kt = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
+    aux["mix1m_8to16_sync_call_us_p50"] = round(statistics.median(lat) * 1e6, 1)
+    aux["mix1m_8to16_kernel_us"] = round(kt * 1e6, 1)
+    aux["mix1m_8to16_kernel_input_GBps"] = round(small.data.size / kt / 1e9, 1)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(bufs, args.cpu_sample_mib << 20)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"five {args.size_mib} MiB script-mix buffers (ascii, latin, cyrillic, cjk, emoji) "
+                               "plus invalid variants (error rate 1e-6), UTF-8->UTF-16LE and UTF-16LE->UTF-8, "
+                               "validating",
+                   "buffers_per_step": len(bufs), "input_bytes_per_step": in_bytes,
+                   "buffer_bytes": size, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"per_buffer": per, "aux": aux, "kernel_hash": kernel_hash(),
+                   "device": torch.cuda.get_device_name(0), "host_cores": os.cpu_count()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

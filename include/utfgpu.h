@@ -1,0 +1,176 @@
+/*
+ * utfgpu.h -- C ABI of the MI355X (gfx950) UTF-8 <-> UTF-16LE library.
+ *
+ * The library validates UTF-8 and UTF-16LE text and transcodes it in both
+ * directions, always validating, as stated in Lemire, "Unicode at Gigabytes
+ * per Second" (Section 1: both formats must be validated and converted;
+ * Section 5: every transcoding includes validation).  The formats are the
+ * ones of Section 3: UTF-8 leading-byte patterns and six validity rules, and
+ * UTF-16 with surrogate pairs.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All text and result pointers are DEVICE pointers (memory of the current
+ *    HIP device).  The caller owns them; the library never frees them and
+ *    never writes to an input.
+ *  - `stream` is a hipStream_t passed as `void*`; NULL means the default
+ *    stream.  Calls on distinct streams may run concurrently (the library
+ *    keeps one workspace per device and stream).  Two calls on the same
+ *    stream run in stream order.
+ *  - UTF-8 text is a byte array of any alignment.  UTF-16LE text and UTF-16
+ *    output are arrays of 16-bit little-endian words and must be 2-byte
+ *    aligned.
+ *  - Sizes are counted in units of the format: bytes for UTF-8, 16-bit
+ *    words for UTF-16.  Inputs may be empty (n == 0); then no kernel runs.
+ *  - Synchronous calls return after the result is known (they synchronise
+ *    `stream`).  The `_async` forms only enqueue work and write their result
+ *    to a device pointer when the stream reaches it.
+ *  - Errors never cause writes outside [out, out + out_cap).
+ *
+ * Result and status codes
+ * -----------------------
+ *  utf_result.status == UTF_OK (0): `count` is the number of input units
+ *      validated (validate_*) or output units written (convert_*).
+ *  1..8 (data errors): the input is invalid; `count` is the offset, in input
+ *      units, of the first character that cannot be read: the length of the
+ *      longest valid prefix.  The kind is the first rule of Section 3 broken
+ *      by that character, checked in the order rule 1, rule 3, rule 2, then
+ *      rules 4, 5, 6 on the decoded value; for UTF-16 an unpaired high or
+ *      low surrogate.
+ *  UTF_OUTPUT_TOO_SMALL (9): the input is valid but the conversion needs
+ *      more than `out_cap` units; `count` is the number needed.  A data error
+ *      takes precedence over this status.
+ *  negative values: misuse or runtime failure (null pointer with n > 0,
+ *      misaligned UTF-16 pointer, size above the supported maximum, HIP
+ *      error); `count` is 0 and nothing was launched unless the status is
+ *      UTF_ERR_HIP.
+ */
+#ifndef UTFGPU_H
+#define UTFGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct utf_result {
+    int32_t status;
+    uint64_t count;
+} utf_result;
+
+enum {
+    UTF_OK = 0,
+    UTF_TOO_SHORT = 1,        /* rule 2: leading byte without enough continuation bytes */
+    UTF_TOO_LONG = 2,         /* rule 3: continuation byte without a leading byte */
+    UTF_OVERLONG = 3,         /* rule 4: value encoded with more bytes than needed */
+    UTF_TOO_LARGE = 4,        /* rule 5: value of 1114112 or more */
+    UTF_SURROGATE = 5,        /* rule 6: value in U+D800..U+DFFF */
+    UTF_HEADER_BITS = 6,      /* rule 1: byte 0xF8..0xFF */
+    UTF_UNPAIRED_HIGH = 7,    /* UTF-16: high surrogate not followed by a low one */
+    UTF_UNPAIRED_LOW = 8,     /* UTF-16: low surrogate not preceded by a high one */
+    UTF_OUTPUT_TOO_SMALL = 9, /* valid input, output capacity too small */
+    UTF_ERR_NULL = -1,
+    UTF_ERR_ALIGN = -2,
+    UTF_ERR_TOO_BIG = -3,
+    UTF_ERR_HIP = -4
+};
+
+/* Largest supported input: 2^40 - 1 UTF-8 bytes, 2^38 - 1 UTF-16 words. */
+#define UTF_MAX_UTF8_BYTES ((uint64_t)1 << 40)
+#define UTF_MAX_UTF16_WORDS ((uint64_t)1 << 38)
+
+/* ---------------------------------------------------------------------- */
+/* Validation (Section 3 rules)                                           */
+/* ---------------------------------------------------------------------- */
+
+/* Validate n bytes of UTF-8 at `in`.  {UTF_OK, n} or {kind, first error}. */
+utf_result validate_utf8(const uint8_t *in, uint64_t n, void *stream);
+
+/* Validate m 16-bit words of UTF-16LE at `in` (2-byte aligned). */
+utf_result validate_utf16le(const uint16_t *in, uint64_t m, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Output lengths                                                         */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Number of UTF-16 words the conversion of `in` writes: one per byte that is
+ * not a continuation byte (10xxxxxx), plus one more per byte >= 0xF0 (a
+ * four-byte character becomes a surrogate pair).  Exact for valid input;
+ * defined by the same per-byte count for any input.  Does not validate.
+ * Returns UINT64_MAX on misuse or HIP error.
+ */
+uint64_t utf16_length_from_utf8(const uint8_t *in, uint64_t n, void *stream);
+
+/*
+ * Number of UTF-8 bytes the conversion of `in` writes: 1 per word below
+ * 0x80, 2 below 0x800, 2 per surrogate word (4 per pair), 3 otherwise.
+ * Exact for valid input; same per-word count for any input.  Does not
+ * validate.  Returns UINT64_MAX on misuse or HIP error.
+ */
+uint64_t utf8_length_from_utf16le(const uint16_t *in, uint64_t m, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Conversions (always validating)                                        */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * UTF-8 -> UTF-16LE.  `out` has room for `out_cap` words (2-byte aligned;
+ * may be NULL when out_cap == 0).  Returns {UTF_OK, words written},
+ * {kind, first error} or {UTF_OUTPUT_TOO_SMALL, words needed}.  On a data
+ * error, out[0 .. words of the valid prefix) holds the conversion of the
+ * valid prefix (cut at out_cap); other output words inside out_cap are
+ * unspecified.  On UTF_OUTPUT_TOO_SMALL out[0 .. out_cap) holds the first
+ * out_cap words of the conversion.  out_cap >= n always suffices.
+ */
+utf_result convert_utf8_to_utf16le(const uint8_t *in, uint64_t n, uint16_t *out,
+                                   uint64_t out_cap, void *stream);
+
+/*
+ * UTF-16LE -> UTF-8, same conventions with `out_cap` in bytes.
+ * out_cap >= 3 * m always suffices.
+ */
+utf_result convert_utf16le_to_utf8(const uint16_t *in, uint64_t m, uint8_t *out,
+                                   uint64_t out_cap, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Asynchronous forms                                                     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Same work as the synchronous calls, enqueued on `stream` without waiting.
+ * The result is written to the device pointer `result` (a utf_result, or a
+ * uint64_t for the length queries) when the stream reaches it.  The return
+ * value is UTF_OK when the work was enqueued, or a negative status (nothing
+ * enqueued).  For n == 0 the result is written with a small device copy.
+ */
+int32_t validate_utf8_async(const uint8_t *in, uint64_t n, utf_result *result, void *stream);
+int32_t validate_utf16le_async(const uint16_t *in, uint64_t m, utf_result *result, void *stream);
+int32_t utf16_length_from_utf8_async(const uint8_t *in, uint64_t n, uint64_t *result, void *stream);
+int32_t utf8_length_from_utf16le_async(const uint16_t *in, uint64_t m, uint64_t *result, void *stream);
+int32_t convert_utf8_to_utf16le_async(const uint8_t *in, uint64_t n, uint16_t *out,
+                                      uint64_t out_cap, utf_result *result, void *stream);
+int32_t convert_utf16le_to_utf8_async(const uint16_t *in, uint64_t m, uint8_t *out,
+                                      uint64_t out_cap, utf_result *result, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Library state                                                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Free every workspace the library holds (per device and stream: tile
+ * status words, control block, result slots).  Must not overlap with calls
+ * in flight.  Later calls allocate again.  Returns UTF_OK or UTF_ERR_HIP.
+ */
+int32_t utfgpu_release_workspace(void);
+
+/* Library version string, e.g. "utfgpu 0.1 gfx950". */
+const char *utfgpu_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTFGPU_H */

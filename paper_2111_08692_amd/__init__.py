@@ -1,0 +1,242 @@
+"""Python binding of ``libutfgpu.so``, the gfx950 UTF-8 <-> UTF-16LE library.
+
+Argument marshalling only: every step of validation, length computation and
+conversion runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors on ``cuda``) and streams.  The functions carry the names of
+the C ABI in ``include/utfgpu.h``:
+
+* ``validate_utf8(t)`` / ``validate_utf16le(t)`` -> ``(status, count)``
+* ``utf16_length_from_utf8(t)`` / ``utf8_length_from_utf16le(t)`` -> int
+* ``convert_utf8_to_utf16le(t, out=None)`` -> ``(status, count, out)``
+* ``convert_utf16le_to_utf8(t, out=None)`` -> ``(status, count, out)``
+
+UTF-8 tensors are ``torch.uint8``; UTF-16LE tensors have 2-byte elements
+(``torch.int16`` by default: the library only reads the bytes).  All must be contiguous CUDA (HIP) tensors.  The
+library is loaded from this directory on first use and every call raises
+if it was not built, so no call can silently fall back to another
+implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libutfgpu.so")
+
+OK = 0
+TOO_SHORT = 1
+TOO_LONG = 2
+OVERLONG = 3
+TOO_LARGE = 4
+SURROGATE = 5
+HEADER_BITS = 6
+UNPAIRED_HIGH = 7
+UNPAIRED_LOW = 8
+OUTPUT_TOO_SMALL = 9
+ERR_NULL = -1
+ERR_ALIGN = -2
+ERR_TOO_BIG = -3
+ERR_HIP = -4
+
+STATUS_NAMES = {
+    OK: "OK", TOO_SHORT: "TOO_SHORT", TOO_LONG: "TOO_LONG", OVERLONG: "OVERLONG",
+    TOO_LARGE: "TOO_LARGE", SURROGATE: "SURROGATE", HEADER_BITS: "HEADER_BITS",
+    UNPAIRED_HIGH: "UNPAIRED_HIGH", UNPAIRED_LOW: "UNPAIRED_LOW",
+    OUTPUT_TOO_SMALL: "OUTPUT_TOO_SMALL", ERR_NULL: "ERR_NULL", ERR_ALIGN: "ERR_ALIGN",
+    ERR_TOO_BIG: "ERR_TOO_BIG", ERR_HIP: "ERR_HIP",
+}
+
+EXPORTS = (
+    "validate_utf8", "validate_utf16le", "utf16_length_from_utf8", "utf8_length_from_utf16le",
+    "convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
+    "validate_utf8_async", "validate_utf16le_async", "utf16_length_from_utf8_async",
+    "utf8_length_from_utf16le_async", "convert_utf8_to_utf16le_async",
+    "convert_utf16le_to_utf8_async", "utfgpu_release_workspace", "utfgpu_version",
+)
+
+
+class UtfResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("count", ctypes.c_uint64)]
+
+
+def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
+    P, U64, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32
+    sig = {
+        "validate_utf8": ([P, U64, P], UtfResult),
+        "validate_utf16le": ([P, U64, P], UtfResult),
+        "utf16_length_from_utf8": ([P, U64, P], U64),
+        "utf8_length_from_utf16le": ([P, U64, P], U64),
+        "convert_utf8_to_utf16le": ([P, U64, P, U64, P], UtfResult),
+        "convert_utf16le_to_utf8": ([P, U64, P, U64, P], UtfResult),
+        "validate_utf8_async": ([P, U64, P, P], I32),
+        "validate_utf16le_async": ([P, U64, P, P], I32),
+        "utf16_length_from_utf8_async": ([P, U64, P, P], I32),
+        "utf8_length_from_utf16le_async": ([P, U64, P, P], I32),
+        "convert_utf8_to_utf16le_async": ([P, U64, P, U64, P, P], I32),
+        "convert_utf16le_to_utf8_async": ([P, U64, P, U64, P, P], I32),
+        "utfgpu_release_workspace": ([], I32),
+        "utfgpu_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with paper_2111_08692_amd.build.build() "
+            "(hipcc --offload-arch=gfx950); there is no other implementation")
+    return _declare(ctypes.CDLL(LIB_PATH))
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load() -> ctypes.CDLL:
+    """The loaded library (loads it on first use; raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def version() -> str:
+    return load().utfgpu_version().decode()
+
+
+def release_workspace() -> int:
+    return int(load().utfgpu_release_workspace())
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev(t: torch.Tensor, elem: int, what: str) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.element_size() != elem:
+        raise ValueError(f"{what} must have {elem}-byte elements")
+
+
+def _ptr(t: Optional[torch.Tensor]) -> int:
+    return 0 if t is None or t.numel() == 0 else t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# the C ABI, one function each
+# ---------------------------------------------------------------------------
+
+def validate_utf8(data: torch.Tensor, stream=None) -> Tuple[int, int]:
+    _dev(data, 1, "data")
+    r = load().validate_utf8(_ptr(data), data.numel(), _stream(stream))
+    return r.status, r.count
+
+
+def validate_utf16le(data: torch.Tensor, stream=None) -> Tuple[int, int]:
+    _dev(data, 2, "data")
+    r = load().validate_utf16le(_ptr(data), data.numel(), _stream(stream))
+    return r.status, r.count
+
+
+def utf16_length_from_utf8(data: torch.Tensor, stream=None) -> int:
+    _dev(data, 1, "data")
+    return int(load().utf16_length_from_utf8(_ptr(data), data.numel(), _stream(stream)))
+
+
+def utf8_length_from_utf16le(data: torch.Tensor, stream=None) -> int:
+    _dev(data, 2, "data")
+    return int(load().utf8_length_from_utf16le(_ptr(data), data.numel(), _stream(stream)))
+
+
+def convert_utf8_to_utf16le(data: torch.Tensor, out: Optional[torch.Tensor] = None,
+                            out_cap: Optional[int] = None, stream=None):
+    """Returns ``(status, count, out)``; ``out`` defaults to ``data.numel()``
+    words (int16 storage)."""
+    _dev(data, 1, "data")
+    if out is None:
+        out = torch.empty(max(data.numel(), 1), dtype=torch.int16, device=data.device)
+    _dev(out, 2, "out")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    r = load().convert_utf8_to_utf16le(_ptr(data), data.numel(), _ptr(out), cap, _stream(stream))
+    return r.status, r.count, out
+
+
+def convert_utf16le_to_utf8(data: torch.Tensor, out: Optional[torch.Tensor] = None,
+                            out_cap: Optional[int] = None, stream=None):
+    """Returns ``(status, count, out)``; ``out`` defaults to ``3 * data.numel()`` bytes."""
+    _dev(data, 2, "data")
+    if out is None:
+        out = torch.empty(max(3 * data.numel(), 1), dtype=torch.uint8, device=data.device)
+    _dev(out, 1, "out")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    r = load().convert_utf16le_to_utf8(_ptr(data), data.numel(), _ptr(out), cap, _stream(stream))
+    return r.status, r.count, out
+
+
+# asynchronous forms: results land in device tensors (int64[2] per utf_result)
+
+def result_tensor(device="cuda") -> torch.Tensor:
+    """Device storage for one ``utf_result`` (status in the low word of [0])."""
+    return torch.zeros(2, dtype=torch.int64, device=device)
+
+
+def decode_result(t: torch.Tensor) -> Tuple[int, int]:
+    v = t.cpu().tolist()
+    status = v[0] & 0xFFFFFFFF
+    if status >= 1 << 31:
+        status -= 1 << 32
+    return status, v[1] & 0xFFFFFFFFFFFFFFFF
+
+
+def validate_utf8_async(data, result, stream=None) -> int:
+    _dev(data, 1, "data")
+    return int(load().validate_utf8_async(_ptr(data), data.numel(), result.data_ptr(), _stream(stream)))
+
+
+def validate_utf16le_async(data, result, stream=None) -> int:
+    _dev(data, 2, "data")
+    return int(load().validate_utf16le_async(_ptr(data), data.numel(), result.data_ptr(), _stream(stream)))
+
+
+def utf16_length_from_utf8_async(data, result, stream=None) -> int:
+    _dev(data, 1, "data")
+    return int(load().utf16_length_from_utf8_async(_ptr(data), data.numel(), result.data_ptr(), _stream(stream)))
+
+
+def utf8_length_from_utf16le_async(data, result, stream=None) -> int:
+    _dev(data, 2, "data")
+    return int(load().utf8_length_from_utf16le_async(_ptr(data), data.numel(), result.data_ptr(), _stream(stream)))
+
+
+def convert_utf8_to_utf16le_async(data, out, result, out_cap=None, stream=None) -> int:
+    _dev(data, 1, "data")
+    _dev(out, 2, "out")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    return int(load().convert_utf8_to_utf16le_async(_ptr(data), data.numel(), _ptr(out), cap,
+                                                 result.data_ptr(), _stream(stream)))
+
+
+def convert_utf16le_to_utf8_async(data, out, result, out_cap=None, stream=None) -> int:
+    _dev(data, 2, "data")
+    _dev(out, 1, "out")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    return int(load().convert_utf16le_to_utf8_async(_ptr(data), data.numel(), _ptr(out), cap,
+                                                 result.data_ptr(), _stream(stream)))

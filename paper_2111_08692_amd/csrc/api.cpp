@@ -1,0 +1,366 @@
+// api.cpp -- the C ABI declared in include/utfgpu.h.
+//
+// Argument checks, the frame/head split of the input address, per
+// (device, stream) workspaces (control block, tile status words, result
+// slots), kernel launches and the synchronous result read-back.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/utfgpu.h"
+#include "device_common.hpp"
+
+namespace utfgpu {
+hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
+                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, u64 ntiles,
+                             hipStream_t stream);
+hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, Ctrl *ctrl, u64 *result,
+                               hipStream_t stream);
+hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
+                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, u64 ntiles,
+                              hipStream_t stream);
+hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, Ctrl *ctrl, u64 *result,
+                              hipStream_t stream);
+hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);
+hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);
+}  // namespace utfgpu
+
+using namespace utfgpu;
+
+static_assert(sizeof(utf_result) == sizeof(DevResult), "result layout");
+static_assert(offsetof(utf_result, count) == offsetof(DevResult, count), "result layout");
+
+namespace {
+
+// Epoch values are 22 bits wide; the status array is cleared whenever the
+// host has issued this many tile launches on a workspace, so no stale word
+// from an earlier call can carry the current epoch.
+constexpr u64 kClearEvery = 1ull << 21;
+
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Ctrl *ctrl = nullptr;        // device
+    DevResult *dres = nullptr;   // device result slot
+    u64 *dlen = nullptr;         // device length slot
+    DevResult *hres = nullptr;   // pinned host copy
+    u64 *hlen = nullptr;         // pinned host copy
+    u64 *status = nullptr;       // device tile status words
+    u64 status_cap = 0;
+    u64 launches = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+void free_ws(Workspace *w) {
+    if (w->ctrl) (void)hipFree(w->ctrl);
+    if (w->dres) (void)hipFree(w->dres);
+    if (w->dlen) (void)hipFree(w->dlen);
+    if (w->status) (void)hipFree(w->status);
+    if (w->hres) (void)hipHostFree(w->hres);
+    if (w->hlen) (void)hipHostFree(w->hlen);
+    delete w;
+}
+
+hipError_t make_ws(int dev, hipStream_t s, Workspace **out) {
+    Workspace *w = new Workspace();
+    w->device = dev;
+    w->stream = s;
+    hipError_t e;
+    if ((e = hipMalloc(&w->ctrl, sizeof(Ctrl))) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&w->dres, sizeof(DevResult))) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&w->dlen, sizeof(u64))) != hipSuccess) goto fail;
+    if ((e = hipHostMalloc(&w->hres, sizeof(DevResult), hipHostMallocDefault)) != hipSuccess) goto fail;
+    if ((e = hipHostMalloc(&w->hlen, sizeof(u64), hipHostMallocDefault)) != hipSuccess) goto fail;
+    {
+        Ctrl init = {};
+        init.err = ~0ull;
+        init.epoch = 1;
+        if ((e = hipMemcpy(w->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice)) != hipSuccess) goto fail;
+    }
+    *out = w;
+    return hipSuccess;
+fail:
+    free_ws(w);
+    return e;
+}
+
+// Workspace of (current device, stream) with room for `ntiles` status words.
+hipError_t get_ws(hipStream_t s, u64 ntiles, Workspace **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto key = std::make_pair(dev, s);
+    auto it = g_ws.find(key);
+    Workspace *w;
+    if (it == g_ws.end()) {
+        if ((e = make_ws(dev, s, &w)) != hipSuccess) return e;
+        g_ws[key] = w;
+    } else {
+        w = it->second;
+    }
+    if (ntiles > w->status_cap) {
+        // the old array may still be read by work queued on this stream
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (w->status) (void)hipFree(w->status);
+        w->status = nullptr;
+        w->status_cap = 0;
+        u64 cap = ntiles < 4096 ? 4096 : ntiles + ntiles / 4;
+        if ((e = hipMalloc(&w->status, cap * sizeof(u64))) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(w->status, 0, cap * sizeof(u64), s)) != hipSuccess) return e;
+        w->status_cap = cap;
+    }
+    if (ntiles > 0) {
+        if (w->launches > 0 && w->launches % kClearEvery == 0) {
+            if ((e = hipMemsetAsync(w->status, 0, w->status_cap * sizeof(u64), s)) != hipSuccess) return e;
+        }
+        w->launches++;
+    }
+    *out = w;
+    return hipSuccess;
+}
+
+inline utf_result mk(int32_t st, u64 c) {
+    utf_result r;
+    r.status = st;
+    r.count = c;
+    return r;
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- argument checks ----------------------------------------------------
+int32_t check8(const uint8_t *in, u64 n) {
+    if (n == 0) return UTF_OK;
+    if (!in) return UTF_ERR_NULL;
+    if (n >= UTF_MAX_UTF8_BYTES) return UTF_ERR_TOO_BIG;
+    return UTF_OK;
+}
+
+int32_t check16(const uint16_t *in, u64 m) {
+    if (m == 0) return UTF_OK;
+    if (!in) return UTF_ERR_NULL;
+    if (reinterpret_cast<uintptr_t>(in) & 1u) return UTF_ERR_ALIGN;
+    if (m >= UTF_MAX_UTF16_WORDS) return UTF_ERR_TOO_BIG;
+    return UTF_OK;
+}
+
+inline const uint8_t *frame_of(const void *p) {
+    return reinterpret_cast<const uint8_t *>(reinterpret_cast<uintptr_t>(p) & ~uintptr_t(15));
+}
+inline long long head_bytes(const void *p) { return (long long)(reinterpret_cast<uintptr_t>(p) & 15u); }
+
+u64 tiles8(long long head, u64 n) { return (u64)((head + (long long)n + 3 + kTileBytes - 1) / kTileBytes); }
+u64 tiles16(long long head_units, u64 m) {
+    const long long units_per_tile = kTileBytes / 2;
+    return (u64)((head_units + (long long)m + units_per_tile - 1) / units_per_tile);
+}
+
+// ---- enqueue helpers (return a negative status or UTF_OK) ----------------
+int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 out_cap, DevResult *res,
+                     hipStream_t s, Workspace **wso) {
+    const long long head = head_bytes(in);
+    const u64 nt = tiles8(head, n);
+    Workspace *w;
+    if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
+    if (!res) res = w->dres;
+    if (launch_utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, nt,
+                          s) != hipSuccess)
+        return UTF_ERR_HIP;
+    *wso = w;
+    return UTF_OK;
+}
+
+int32_t enqueue_utf16(bool convert, const uint16_t *in, u64 m, uint8_t *out, u64 out_cap, DevResult *res,
+                      hipStream_t s, Workspace **wso) {
+    const long long head = head_bytes(in) / 2;
+    const u64 nt = tiles16(head, m);
+    Workspace *w;
+    if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
+    if (!res) res = w->dres;
+    if (launch_utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, nt,
+                           s) != hipSuccess)
+        return UTF_ERR_HIP;
+    *wso = w;
+    return UTF_OK;
+}
+
+utf_result read_result(Workspace *w, hipStream_t s) {
+    if (hipMemcpyAsync(w->hres, w->dres, sizeof(DevResult), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return mk(UTF_ERR_HIP, 0);
+    if (hipStreamSynchronize(s) != hipSuccess) return mk(UTF_ERR_HIP, 0);
+    return mk(w->hres->status, w->hres->count);
+}
+
+u64 read_len(Workspace *w, hipStream_t s) {
+    if (hipMemcpyAsync(w->hlen, w->dlen, sizeof(u64), hipMemcpyDeviceToHost, s) != hipSuccess) return ~0ull;
+    if (hipStreamSynchronize(s) != hipSuccess) return ~0ull;
+    return *w->hlen;
+}
+
+}  // namespace
+
+extern "C" {
+
+utf_result validate_utf8(const uint8_t *in, uint64_t n, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return mk(c, 0);
+    if (n == 0) return mk(UTF_OK, 0);
+    Workspace *w;
+    hipStream_t s = as_stream(stream);
+    if ((c = enqueue_utf8(false, in, n, nullptr, 0, nullptr, s, &w)) != UTF_OK) return mk(c, 0);
+    return read_result(w, s);
+}
+
+utf_result validate_utf16le(const uint16_t *in, uint64_t m, void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return mk(c, 0);
+    if (m == 0) return mk(UTF_OK, 0);
+    Workspace *w;
+    hipStream_t s = as_stream(stream);
+    if ((c = enqueue_utf16(false, in, m, nullptr, 0, nullptr, s, &w)) != UTF_OK) return mk(c, 0);
+    return read_result(w, s);
+}
+
+utf_result convert_utf8_to_utf16le(const uint8_t *in, uint64_t n, uint16_t *out, uint64_t out_cap,
+                                   void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return mk(c, 0);
+    if (!out && out_cap > 0) return mk(UTF_ERR_NULL, 0);
+    if (reinterpret_cast<uintptr_t>(out) & 1u) return mk(UTF_ERR_ALIGN, 0);
+    if (n == 0) return mk(UTF_OK, 0);
+    Workspace *w;
+    hipStream_t s = as_stream(stream);
+    if ((c = enqueue_utf8(true, in, n, out, out_cap, nullptr, s, &w)) != UTF_OK) return mk(c, 0);
+    return read_result(w, s);
+}
+
+utf_result convert_utf16le_to_utf8(const uint16_t *in, uint64_t m, uint8_t *out, uint64_t out_cap,
+                                   void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return mk(c, 0);
+    if (!out && out_cap > 0) return mk(UTF_ERR_NULL, 0);
+    if (m == 0) return mk(UTF_OK, 0);
+    Workspace *w;
+    hipStream_t s = as_stream(stream);
+    if ((c = enqueue_utf16(true, in, m, out, out_cap, nullptr, s, &w)) != UTF_OK) return mk(c, 0);
+    return read_result(w, s);
+}
+
+uint64_t utf16_length_from_utf8(const uint8_t *in, uint64_t n, void *stream) {
+    if (check8(in, n) != UTF_OK) return ~0ull;
+    if (n == 0) return 0;
+    hipStream_t s = as_stream(stream);
+    Workspace *w;
+    if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
+    if (launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->ctrl, w->dlen, s) != hipSuccess)
+        return ~0ull;
+    return read_len(w, s);
+}
+
+uint64_t utf8_length_from_utf16le(const uint16_t *in, uint64_t m, void *stream) {
+    if (check16(in, m) != UTF_OK) return ~0ull;
+    if (m == 0) return 0;
+    hipStream_t s = as_stream(stream);
+    Workspace *w;
+    if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
+    if (launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->ctrl, w->dlen, s) != hipSuccess)
+        return ~0ull;
+    return read_len(w, s);
+}
+
+int32_t validate_utf8_async(const uint8_t *in, uint64_t n, utf_result *result, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return c;
+    if (!result) return UTF_ERR_NULL;
+    hipStream_t s = as_stream(stream);
+    DevResult *r = reinterpret_cast<DevResult *>(result);
+    if (n == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    return enqueue_utf8(false, in, n, nullptr, 0, r, s, &w);
+}
+
+int32_t validate_utf16le_async(const uint16_t *in, uint64_t m, utf_result *result, void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return c;
+    if (!result) return UTF_ERR_NULL;
+    hipStream_t s = as_stream(stream);
+    DevResult *r = reinterpret_cast<DevResult *>(result);
+    if (m == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    return enqueue_utf16(false, in, m, nullptr, 0, r, s, &w);
+}
+
+int32_t convert_utf8_to_utf16le_async(const uint8_t *in, uint64_t n, uint16_t *out, uint64_t out_cap,
+                                      utf_result *result, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return c;
+    if (!result || (!out && out_cap > 0)) return UTF_ERR_NULL;
+    if (reinterpret_cast<uintptr_t>(out) & 1u) return UTF_ERR_ALIGN;
+    hipStream_t s = as_stream(stream);
+    DevResult *r = reinterpret_cast<DevResult *>(result);
+    if (n == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    return enqueue_utf8(true, in, n, out, out_cap, r, s, &w);
+}
+
+int32_t convert_utf16le_to_utf8_async(const uint16_t *in, uint64_t m, uint8_t *out, uint64_t out_cap,
+                                      utf_result *result, void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return c;
+    if (!result || (!out && out_cap > 0)) return UTF_ERR_NULL;
+    hipStream_t s = as_stream(stream);
+    DevResult *r = reinterpret_cast<DevResult *>(result);
+    if (m == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    return enqueue_utf16(true, in, m, out, out_cap, r, s, &w);
+}
+
+int32_t utf16_length_from_utf8_async(const uint8_t *in, uint64_t n, uint64_t *result, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return c;
+    if (!result) return UTF_ERR_NULL;
+    hipStream_t s = as_stream(stream);
+    if (n == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
+    return launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->ctrl, result, s) == hipSuccess
+               ? UTF_OK
+               : UTF_ERR_HIP;
+}
+
+int32_t utf8_length_from_utf16le_async(const uint16_t *in, uint64_t m, uint64_t *result, void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return c;
+    if (!result) return UTF_ERR_NULL;
+    hipStream_t s = as_stream(stream);
+    if (m == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    Workspace *w;
+    if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
+    return launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->ctrl, result, s) == hipSuccess
+               ? UTF_OK
+               : UTF_ERR_HIP;
+}
+
+int32_t utfgpu_release_workspace(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    int32_t rc = UTF_OK;
+    for (auto &kv : g_ws) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        if (hipSetDevice(kv.first.first) != hipSuccess) rc = UTF_ERR_HIP;
+        if (hipStreamSynchronize(kv.first.second) != hipSuccess) rc = UTF_ERR_HIP;
+        free_ws(kv.second);
+        (void)hipSetDevice(prev);
+    }
+    g_ws.clear();
+    return rc;
+}
+
+const char *utfgpu_version(void) { return "utfgpu 0.1 gfx950"; }
+
+}  // extern "C"

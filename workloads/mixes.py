@@ -91,20 +91,28 @@ CHUNK_CHARS = 1 << 22
 # --------------------------------------------------------------------------
 
 def draw_codepoints(rng: np.random.Generator, mix: str, count: int) -> np.ndarray:
-    """``count`` i.i.d. code points of ``mix`` as uint32."""
+    """``count`` i.i.d. code points of ``mix`` as uint32.
+
+    One uniform number u per character picks both the class (the interval
+    of the cumulative weights u falls in) and the value inside the class
+    (u's position inside that interval, scaled to the class size)."""
     classes = MIXES[mix]
     if len(classes) == 1:
         vals = classes[0][1]
         return vals[rng.integers(0, vals.size, size=count)]
-    weights = np.array([w for w, _ in classes], dtype=np.float64)
-    cls = rng.choice(len(classes), size=count, p=weights / weights.sum())
-    out = np.empty(count, dtype=np.uint32)
-    for c, (_, vals) in enumerate(classes):
-        sel = cls == c
-        k = int(sel.sum())
-        if k:
-            out[sel] = vals[rng.integers(0, vals.size, size=k)]
-    return out
+    w = np.array([c[0] for c in classes], dtype=np.float64)
+    w /= w.sum()
+    hi = np.cumsum(w)
+    hi[-1] = 1.0
+    lo = hi - w
+    sizes = np.array([c[1].size for c in classes], dtype=np.int64)
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    table = np.concatenate([c[1] for c in classes])
+    u = rng.random(count)
+    cls = np.minimum(np.searchsorted(hi, u, side="right"), len(classes) - 1)
+    idx = ((u - lo[cls]) / w[cls] * sizes[cls]).astype(np.int64)
+    idx = np.clip(idx, 0, sizes[cls] - 1)
+    return table[starts[cls] + idx]
 
 
 def _to_str(cps: np.ndarray) -> str:
@@ -170,7 +178,7 @@ def _chunk_pieces(mix: str, encoding: str, seq: np.random.SeedSequence, nchars: 
 
 def make_buffer(mix: str, size_bytes: int, seed: int, encoding: str = "utf-8",
                 error_rate: float = 0.0, error_seed: Optional[int] = None,
-                workers: Optional[int] = None) -> TextBuffer:
+                workers: Optional[int] = None, executor=None) -> TextBuffer:
     """A buffer of exactly ``size_bytes`` bytes of ``mix`` text.
 
     Characters are drawn chunk by chunk (``CHUNK_CHARS`` per chunk, chunk j
@@ -180,6 +188,10 @@ def make_buffer(mix: str, size_bytes: int, seed: int, encoding: str = "utf-8",
     at seeded character indices, kept at least three characters apart, are
     replaced by invalid patterns; ``errors`` lists the unit offset of each
     pattern that made it into the buffer.
+
+    ``executor`` (e.g. a process pool) draws and encodes chunks in
+    parallel; by default a thread pool is used.  The result does not depend
+    on it.
     """
     unit = 1 if encoding == "utf-8" else 2
     assert size_bytes % unit == 0 and size_bytes >= 0
@@ -228,20 +240,24 @@ def make_buffer(mix: str, size_bytes: int, seed: int, encoding: str = "utf-8",
             filled += len(blob)
         return True
 
-    j = 0
-    with ThreadPoolExecutor(max_workers=workers) as ex:
+    own = executor is None
+    ex = ThreadPoolExecutor(max_workers=workers) if own else executor
+    try:
+        j = 0
         full = True
         while full:
             if j >= nchunks:
                 raise RuntimeError("generator ran out of chunks")
             batch = list(range(j, min(j + workers, nchunks)))
-            results = ex.map(lambda c: _chunk_pieces(mix, encoding, seqs[c], CHUNK_CHARS,
-                                                     bad_by_chunk.get(c, [])), batch)
-            for pieces in results:
-                if not place(pieces):
+            futs = [ex.submit(_chunk_pieces, mix, encoding, seqs[c], CHUNK_CHARS, bad_by_chunk.get(c, []))
+                    for c in batch]
+            for f in futs:
+                if full and not place(f.result()):
                     full = False
-                    break
             j = batch[-1] + 1
+    finally:
+        if own:
+            ex.shutdown()
 
     pad = size_bytes - filled
     out[filled:] = 0x20
