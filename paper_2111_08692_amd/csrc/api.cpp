@@ -5,6 +5,7 @@
 // slots), kernel launches and the synchronous result read-back.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -13,21 +14,31 @@
 #include "device_common.hpp"
 
 namespace utfgpu {
+u64 utf8_tiles_for(long long head, long long n);
+u64 utf16_tiles_for(long long head, long long m);
 hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
-                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, u64 ntiles,
-                             hipStream_t stream);
-hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, Ctrl *ctrl, u64 *result,
-                               hipStream_t stream);
+                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);
 hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
-                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, u64 ntiles,
-                              hipStream_t stream);
-hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, Ctrl *ctrl, u64 *result,
-                              hipStream_t stream);
+                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);
+hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, u64 *partials, Ctrl *ctrl,
+                               u64 *result, hipStream_t stream);
+hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,
+                              u64 *result, hipStream_t stream);
 hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);
 hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);
 }  // namespace utfgpu
 
 using namespace utfgpu;
+
+int utfgpu::lookback_spin_limit() {
+    static const int limit = [] {
+        const char *e = std::getenv("UTFGPU_LOOKBACK_SPINS");
+        if (!e || !*e) return kDefaultSpinLimit;
+        const int v = std::atoi(e);
+        return v < 0 ? 0 : (v > 1 << 20 ? 1 << 20 : v);
+    }();
+    return limit;
+}
 
 static_assert(sizeof(utf_result) == sizeof(DevResult), "result layout");
 static_assert(offsetof(utf_result, count) == offsetof(DevResult, count), "result layout");
@@ -47,6 +58,7 @@ struct Workspace {
     u64 *dlen = nullptr;         // device length slot
     DevResult *hres = nullptr;   // pinned host copy
     u64 *hlen = nullptr;         // pinned host copy
+    u64 *partials = nullptr;     // device partial sums of the length reductions
     u64 *status = nullptr;       // device tile status words
     u64 status_cap = 0;
     u64 launches = 0;
@@ -60,6 +72,7 @@ void free_ws(Workspace *w) {
     if (w->dres) (void)hipFree(w->dres);
     if (w->dlen) (void)hipFree(w->dlen);
     if (w->status) (void)hipFree(w->status);
+    if (w->partials) (void)hipFree(w->partials);
     if (w->hres) (void)hipHostFree(w->hres);
     if (w->hlen) (void)hipHostFree(w->hlen);
     delete w;
@@ -73,6 +86,7 @@ hipError_t make_ws(int dev, hipStream_t s, Workspace **out) {
     if ((e = hipMalloc(&w->ctrl, sizeof(Ctrl))) != hipSuccess) goto fail;
     if ((e = hipMalloc(&w->dres, sizeof(DevResult))) != hipSuccess) goto fail;
     if ((e = hipMalloc(&w->dlen, sizeof(u64))) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&w->partials, kMaxPartials * sizeof(u64))) != hipSuccess) goto fail;
     if ((e = hipHostMalloc(&w->hres, sizeof(DevResult), hipHostMallocDefault)) != hipSuccess) goto fail;
     if ((e = hipHostMalloc(&w->hlen, sizeof(u64), hipHostMallocDefault)) != hipSuccess) goto fail;
     {
@@ -154,22 +168,17 @@ inline const uint8_t *frame_of(const void *p) {
 }
 inline long long head_bytes(const void *p) { return (long long)(reinterpret_cast<uintptr_t>(p) & 15u); }
 
-u64 tiles8(long long head, u64 n) { return (u64)((head + (long long)n + 3 + kTileBytes - 1) / kTileBytes); }
-u64 tiles16(long long head_units, u64 m) {
-    const long long units_per_tile = kTileBytes / 2;
-    return (u64)((head_units + (long long)m + units_per_tile - 1) / units_per_tile);
-}
 
 // ---- enqueue helpers (return a negative status or UTF_OK) ----------------
 int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 out_cap, DevResult *res,
                      hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in);
-    const u64 nt = tiles8(head, n);
+    const u64 nt = utf8_tiles_for(head, (long long)n);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (launch_utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, nt,
-                          s) != hipSuccess)
+    if (launch_utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, s) !=
+        hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
     return UTF_OK;
@@ -178,12 +187,12 @@ int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 
 int32_t enqueue_utf16(bool convert, const uint16_t *in, u64 m, uint8_t *out, u64 out_cap, DevResult *res,
                       hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in) / 2;
-    const u64 nt = tiles16(head, m);
+    const u64 nt = utf16_tiles_for(head, (long long)m);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (launch_utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, nt,
-                           s) != hipSuccess)
+    if (launch_utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, s) !=
+        hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
     return UTF_OK;
@@ -257,7 +266,8 @@ uint64_t utf16_length_from_utf8(const uint8_t *in, uint64_t n, void *stream) {
     hipStream_t s = as_stream(stream);
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
-    if (launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->ctrl, w->dlen, s) != hipSuccess)
+    if (launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, w->dlen, s) !=
+        hipSuccess)
         return ~0ull;
     return read_len(w, s);
 }
@@ -268,7 +278,8 @@ uint64_t utf8_length_from_utf16le(const uint16_t *in, uint64_t m, void *stream) 
     hipStream_t s = as_stream(stream);
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
-    if (launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->ctrl, w->dlen, s) != hipSuccess)
+    if (launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, w->dlen, s) !=
+        hipSuccess)
         return ~0ull;
     return read_len(w, s);
 }
@@ -328,7 +339,8 @@ int32_t utf16_length_from_utf8_async(const uint8_t *in, uint64_t n, uint64_t *re
     if (n == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
-    return launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->ctrl, result, s) == hipSuccess
+    return launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, result, s) ==
+                   hipSuccess
                ? UTF_OK
                : UTF_ERR_HIP;
 }
@@ -341,7 +353,8 @@ int32_t utf8_length_from_utf16le_async(const uint16_t *in, uint64_t m, uint64_t 
     if (m == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
-    return launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->ctrl, result, s) == hipSuccess
+    return launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, result, s) ==
+                   hipSuccess
                ? UTF_OK
                : UTF_ERR_HIP;
 }

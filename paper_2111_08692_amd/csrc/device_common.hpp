@@ -1,12 +1,10 @@
 // device_common.hpp -- shared device machinery of the gfx950 UTF kernels.
 //
-// Geometry.  A workgroup is 256 lanes (four wave64 waves).  Every lane
+// Geometry.  A workgroup is kWaves wave64 waves.  Every lane
 // loads kRows 16-byte chunks; the chunks of one row of one wave are
 // contiguous (1 KiB per row, coalesced dwordx4 loads), the rows of a wave
 // follow each other, and the waves of a workgroup follow each other, so a
-// tile is kTileBytes contiguous input bytes.  Tiles are numbered in input
-// order by an atomic ticket, which makes the single-pass scan below
-// deadlock-free whatever order the hardware starts workgroups in.
+// tile is kTileBytes contiguous input bytes.  Tile t is workgroup t.
 //
 // Buffers are addressed through an aligned "frame": frame = input address
 // rounded down to 16 bytes, head = input address - frame.  Input unit i sits
@@ -18,7 +16,14 @@
 // lanes -> wave (shuffles) -> workgroup (LDS) -> device (decoupled
 // look-back over one 64-bit status word per tile: 2 flag bits, 22 epoch
 // bits, 40 value bits).  The epoch tags the words written by one call, so
-// the status array is never cleared between calls.
+// the status array is never cleared between calls.  A wave that waits too
+// long for a predecessor's word computes that tile's aggregate itself and
+// publishes it, so no wait depends on the order in which the hardware
+// starts workgroups.
+//
+// Nothing in a tile's path uses a device-scope fence (on gfx950 those write
+// back and invalidate the L2) or a shared counter: the result of a call is
+// formed by a one-workgroup finalize kernel queued after the tile kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,14 +31,18 @@
 
 namespace utfgpu {
 
+// Tiles of 64 KiB: the decoupled look-back costs one status round trip
+// per tile, which smaller tiles cannot hide at full HBM bandwidth.
 constexpr int kWave = 64;
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / kWave;
+constexpr int kWaves = 16;
+constexpr int kBlock = kWaves * kWave;             // 1024 lanes
 constexpr int kRows = 4;
+constexpr int kGroup = 1;                          // rows staged at a time
 constexpr int kChunk = 16;
 constexpr int kRowBytes = kWave * kChunk;          // 1024
 constexpr int kWaveBytes = kRows * kRowBytes;      // 4096
-constexpr int kTileBytes = kWaves * kWaveBytes;    // 16384
+constexpr int kTileBytes = kWaves * kWaveBytes;    // 65536
+constexpr int kMaxPartials = 2048;                 // workgroups of the length reductions
 
 // Status codes; the same values as the public header.
 enum : uint32_t {
@@ -59,16 +68,16 @@ struct DevResult {
     u64 count;
 };
 
-// Per-workspace control block.  Every call leaves it as it found it: the
-// last workgroup to finish resets the ticket, the done counter, the error
-// word and the total, and advances the epoch.
+// Per-workspace control block, each field on its own 64-byte line.  The
+// finalize kernel of every call resets `err` and `total` and advances
+// `epoch`, so each call finds it in the same state.
 struct Ctrl {
-    u64 ticket;     // next tile number
-    u64 done;       // workgroups finished
     u64 err;        // min over (position << 4 | kind); ~0 when no error
-    u64 total;      // output units of the whole call
+    u64 pad0[7];
+    u64 total;      // output units of the whole call (written by the last tile)
+    u64 pad1[7];
     u64 epoch;      // tag of the status words of the current call
-    u64 pad[3];
+    u64 pad2[7];
 };
 
 // ------------------------------------------------------------------------
@@ -80,11 +89,12 @@ __device__ __forceinline__ u64 ld_agent(u64 *p) {
 __device__ __forceinline__ void st_agent(u64 *p, u64 v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ u64 add_agent(u64 *p, u64 v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void min_agent(u64 *p, u64 v) {
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_agent(u64 *p, u64 expected, u64 desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------------
@@ -123,8 +133,12 @@ __device__ __forceinline__ u64 wave_min_u64(u64 v) {
     return v;
 }
 
-// byte k (0..3) of a dword
-__device__ __forceinline__ uint32_t byte_of(uint32_t x, int k) { return (x >> (8 * k)) & 0xFFu; }
+// LDS written by some lanes of a wave becomes readable by the others.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // bytes k..k+3 of the 8-byte little-endian pair (lo, hi)
 __device__ __forceinline__ uint32_t window4(uint32_t lo, uint32_t hi, int k) {
@@ -151,6 +165,7 @@ constexpr u64 kFlagAggregate = 1ull;
 constexpr u64 kFlagPrefix = 2ull;
 constexpr u64 kEpochMask = (1ull << 22) - 1;
 constexpr u64 kValueMask = (1ull << 40) - 1;
+constexpr int kDefaultSpinLimit = 48;   // probes (about 1 us each) before helping
 
 __device__ __forceinline__ u64 pack_status(u64 flag, u64 epoch, u64 value) {
     return (flag << 62) | ((epoch & kEpochMask) << 40) | (value & kValueMask);
@@ -159,91 +174,92 @@ __device__ __forceinline__ bool status_ready(u64 s, u64 epoch) {
     return (s >> 62) != 0 && ((s >> 40) & kEpochMask) == (epoch & kEpochMask);
 }
 
-// Exclusive prefix of tile t (t > 0): run by one whole wave.  Lane j looks
-// at tile t-1-j; once a window of 64 predecessors has published, the sum
-// runs from the nearest predecessor that carries an inclusive prefix.
-__device__ __noinline__ u64 lookback(u64 *status, long long t, u64 epoch) {
+// Exclusive prefix of tile t (t > 0), run by one whole wave.  Lane j looks
+// at tile t-1-j.  The sum runs from the nearest predecessor that carries an
+// inclusive prefix, so only the tiles up to that one must have published;
+// if none of the 64 does, their aggregates are added and the window moves
+// back.  If a needed predecessor stays silent for `spin_limit` probes, the
+// wave computes its aggregate with `agg(tile)` (a wave-wide call returning
+// the same value in every lane) and publishes it unless the owner has done
+// so meanwhile.
+template <class Agg>
+__device__ __forceinline__ u64 lookback(u64 *status, long long t, u64 epoch, int spin_limit, Agg agg) {
     const uint32_t lane = lane_id();
     u64 excl = 0;
-    long long j = t - 1;
-    for (;;) {
-        long long idx = j - (long long)lane;
-        u64 s;
-        if (idx >= 0) {
-            s = ld_agent(status + idx);
-            while (!status_ready(s, epoch)) {
-                __builtin_amdgcn_s_sleep(1);
-                s = ld_agent(status + idx);
+    for (long long j = t - 1;; j -= kWave) {
+        const long long idx = j - (long long)lane;
+        u64 s = idx >= 0 ? ld_agent(status + idx) : pack_status(kFlagPrefix, epoch, 0);
+        for (int spins = 0;;) {
+            const bool ready = idx < 0 || status_ready(s, epoch);
+            const u64 waiting = __ballot(!ready);
+            const u64 pmask = __ballot(ready && (s >> 62) == kFlagPrefix);
+            const u64 low = pmask & (~pmask + 1);                 // nearest prefix
+            const u64 need = pmask ? (low << 1) - 1 : ~0ull;      // lanes up to it
+            const u64 blocking = waiting & need;
+            if (blocking == 0) {
+                const u64 v = ((need >> lane) & 1u) ? (s & kValueMask) : 0;
+                excl += wave_sum_u64(v);
+                if (pmask) return excl;
+                break;
             }
-        } else {
-            s = pack_status(kFlagPrefix, epoch, 0);
+            if (spins >= spin_limit) {
+                const int k = __ffsll((long long)blocking) - 1;
+                const long long miss = j - k;
+                const u64 a = agg(miss);
+                if ((int)lane == k) cas_agent(status + miss, s, pack_status(kFlagAggregate, epoch, a));
+                spins = 0;
+            } else {
+                __builtin_amdgcn_s_sleep(2);
+                ++spins;
+            }
+            if (!ready) s = ld_agent(status + idx);
         }
-        u64 pmask = __ballot((s >> 62) == kFlagPrefix);
-        u64 v = s & kValueMask;
-        if (pmask) {
-            int k = __ffsll((long long)pmask) - 1;
-            if ((int)lane > k) v = 0;
-            return excl + wave_sum_u64(v);
-        }
-        excl += wave_sum_u64(v);
-        j -= kWave;
     }
 }
 
-// Called by one thread per workgroup after all of the workgroup's global
-// effects.  True for the last workgroup of the launch.
-__device__ __forceinline__ bool arrive_last(Ctrl *ctrl, u64 nblocks) {
-    __threadfence();
-    u64 old = __hip_atomic_fetch_add(&ctrl->done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == nblocks - 1) {
-        __threadfence();
-        return true;
+// Publish tile t's aggregate, resolve its exclusive prefix, publish its
+// inclusive prefix.  Run by one whole wave; returns the exclusive prefix.
+template <class Agg>
+__device__ __forceinline__ u64 resolve_prefix(u64 *status, u64 t, u64 epoch, int spin_limit, u64 tile_total,
+                                              Agg agg) {
+    const uint32_t lane = lane_id();
+    if (t == 0) {
+        if (lane == 0) st_agent(status, pack_status(kFlagPrefix, epoch, tile_total));
+        return 0;
     }
-    return false;
-}
-
-__device__ __forceinline__ void reset_ctrl(Ctrl *ctrl) {
-    st_agent(&ctrl->ticket, 0);
-    st_agent(&ctrl->done, 0);
-    st_agent(&ctrl->err, ~0ull);
-    st_agent(&ctrl->total, 0);
-    st_agent(&ctrl->epoch, ld_agent(&ctrl->epoch) + 1);
-    __threadfence();
-}
-
-__device__ __forceinline__ void write_result(DevResult *r, uint32_t status, u64 count) {
-    r->status = (int32_t)status;
-    r->pad = 0;
-    r->count = count;
+    if (lane == 0) st_agent(status + t, pack_status(kFlagAggregate, epoch, tile_total));
+    const u64 prefix = lookback(status, (long long)t, epoch, spin_limit, agg);
+    if (lane == 0) st_agent(status + t, pack_status(kFlagPrefix, epoch, prefix + tile_total));
+    return prefix;
 }
 
 // ------------------------------------------------------------------------
-// Write-out of a tile's staged output
+// Write-out of staged output
 // ------------------------------------------------------------------------
-// The tile's output occupies bytes [g0, g1) of global memory, clamped to
-// the caller's capacity.  `stage` (LDS) holds those bytes starting at
-// stage byte 0 = global byte g0.  Whole 16-byte aligned global blocks are
-// written with one dwordx4 store each; the two partial blocks at the ends
-// are written with stores of `unit` bytes so that neighbouring tiles never
-// touch each other's bytes.  Run by all 256 lanes.
-template <int kUnit>
+// The output occupies bytes [g0, g0 + nbytes) of global memory.  `stage`
+// (LDS, dword aligned) holds those bytes starting at stage byte 0.  Whole
+// 16-byte aligned global blocks are written with one dwordx4 store each;
+// the partial blocks at the two ends are written with stores of kUnit bytes
+// so that neighbouring ranges never touch each other's bytes.  Run by
+// kThreads threads with index `tid`.
+template <int kUnit, int kThreads>
 __device__ __forceinline__ void write_out(uint8_t *g0p, u64 nbytes, const uint32_t *stage, uint32_t tid) {
     if (nbytes == 0) return;
     const uintptr_t g0 = (uintptr_t)g0p;
     const uintptr_t g1 = g0 + nbytes;
     const uintptr_t c0 = g0 & ~(uintptr_t)15;
-    const uintptr_t nblk = ((g1 + 15) & ~(uintptr_t)15) - c0;
+    const uintptr_t cend = (g1 + 15) & ~(uintptr_t)15;
     const uint32_t shift = (uint32_t)((c0 - g0) & 3);   // (c - g0) mod 4 is the same for all blocks
     const uint8_t *sb = (const uint8_t *)stage;
-    for (uintptr_t c = c0 + 16 * (uintptr_t)tid; c < c0 + nblk; c += 16 * kBlock) {
+    for (uintptr_t c = c0 + 16 * (uintptr_t)tid; c < cend; c += 16 * kThreads) {
         if (c >= g0 && c + 16 <= g1) {
-            const long long so = (long long)(c - g0);          // stage byte offset of the block
+            const uintptr_t so = c - g0;          // stage byte offset of the block
             const uint32_t *w = stage + (so >> 2);
             u32x4 v;
             if (shift == 0) {
                 v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
             } else {
-                uint32_t a0 = w[0], a1 = w[1], a2 = w[2], a3 = w[3], a4 = w[4];
+                const uint32_t a0 = w[0], a1 = w[1], a2 = w[2], a3 = w[3], a4 = w[4];
                 v.x = __builtin_amdgcn_alignbyte(a1, a0, shift);
                 v.y = __builtin_amdgcn_alignbyte(a2, a1, shift);
                 v.z = __builtin_amdgcn_alignbyte(a3, a2, shift);
@@ -263,5 +279,18 @@ __device__ __forceinline__ void write_out(uint8_t *g0p, u64 nbytes, const uint32
         }
     }
 }
+
+// ------------------------------------------------------------------------
+// Finalize: one workgroup queued after a tile kernel.
+// ------------------------------------------------------------------------
+enum : int { kFinValidate = 0, kFinConvert = 1, kFinLength = 2 };
+
+hipError_t launch_finalize(Ctrl *ctrl, DevResult *result, u64 *len_result, int mode, u64 n, u64 out_cap,
+                           const u64 *partials, int npartials, hipStream_t stream);
+
+// Look-back probes before a wave computes a silent predecessor's aggregate
+// itself: UTFGPU_LOOKBACK_SPINS when set (0 exercises the helping path on
+// every wait), else kDefaultSpinLimit.
+int lookback_spin_limit();
 
 }  // namespace utfgpu

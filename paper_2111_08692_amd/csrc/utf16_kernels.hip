@@ -20,9 +20,11 @@
 namespace utfgpu {
 
 constexpr int kRowUnits = kRowBytes / 2;       // 512
-constexpr int kWaveUnits = kWaveBytes / 2;     // 2048
-constexpr int kTileUnits = kTileBytes / 2;     // 8192
-constexpr uint32_t kStageBytes16 = 3u * kTileUnits;
+constexpr int kWaveUnits = kWaveBytes / 2;     // 2048 words per wave
+constexpr int kTileUnits = kTileBytes / 2;     // 32768 words per tile
+// bytes one wave stages at a time: at most 3 per word
+constexpr uint32_t kStageBytes = 3u * kGroup * kRowUnits;
+constexpr int kStageWords16 = (int)kStageBytes / 4 + 4;
 
 enum : uint32_t { kAscii16 = 0, kUpTo2B = 1, kBmp = 2, kAnyUnit = 3 };
 
@@ -40,8 +42,8 @@ struct LaneUnits {
     uint32_t next[kRows];   // dword after the chunk (its low half is the word after)
 };
 
-__device__ __forceinline__ void load_tile16(const uint8_t *frame, long long head, long long end,
-                                            long long wbase, uint32_t lane, LaneUnits &t) {
+__device__ __forceinline__ void load_span16(const uint8_t *frame, long long head, long long end, long long wbase,
+                                            uint32_t lane, LaneUnits &t) {
     const bool edge_wave = wbase < head || wbase + kWaveUnits > end;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
@@ -61,8 +63,8 @@ __device__ __forceinline__ void load_tile16(const uint8_t *frame, long long head
         hn = keep_units(*(const uint32_t *)(frame + 2 * (wbase + kWaveUnits)), wbase + kWaveUnits, head, end);
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-        uint32_t p = __shfl_up(t.d[r][3], 1);
-        uint32_t nx = __shfl_down(t.d[r][0], 1);
+        const uint32_t p = __shfl_up(t.d[r][3], 1);
+        const uint32_t nx = __shfl_down(t.d[r][0], 1);
         const uint32_t p0 = r == 0 ? hp : readlane(t.d[r - 1][3], kWave - 1);
         const uint32_t n63 = r == kRows - 1 ? hn : readlane(t.d[r + 1][0], 0);
         t.prev[r] = lane == 0 ? p0 : p;
@@ -74,6 +76,9 @@ __device__ __forceinline__ bool is_sur(uint32_t u) { return (u & 0xF800u) == 0xD
 __device__ __forceinline__ bool is_high(uint32_t u) { return (u & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low(uint32_t u) { return (u & 0xFC00u) == 0xDC00u; }
 
+// Any surrogate among the two words of x.
+__device__ __forceinline__ bool has_sur(uint32_t x) { return is_sur(x & 0xFFFFu) || is_sur(x >> 16); }
+
 __device__ __forceinline__ uint32_t wave_class16(const LaneUnits &t) {
     uint32_t a80 = 0, a800 = 0;
     bool sur = false;
@@ -84,7 +89,7 @@ __device__ __forceinline__ uint32_t wave_class16(const LaneUnits &t) {
             const uint32_t x = t.d[r][k];
             a80 |= x & 0xFF80FF80u;
             a800 |= x & 0xF800F800u;
-            sur = sur || is_sur(x & 0xFFFFu) || is_sur(x >> 16);
+            sur = sur || has_sur(x);
         }
     if (__ballot(sur)) return kAnyUnit;
     if (__ballot(a800 != 0)) return kBmp;
@@ -98,17 +103,15 @@ __device__ __forceinline__ uint32_t width8(uint32_t u) {
     return 1u + (u >= 0x80u) + (u >= 0x800u) - (uint32_t)is_sur(u);
 }
 
-__device__ __forceinline__ uint32_t chunk_width8(const uint32_t (&d)[4]) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w += width8(d[k] & 0xFFFFu) + width8(d[k] >> 16);
-    return w;
+__device__ __forceinline__ uint32_t chunk_width8(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3) {
+    return width8(d0 & 0xFFFFu) + width8(d0 >> 16) + width8(d1 & 0xFFFFu) + width8(d1 >> 16) +
+           width8(d2 & 0xFFFFu) + width8(d2 >> 16) + width8(d3 & 0xFFFFu) + width8(d3 >> 16);
 }
 
 __device__ __forceinline__ uint32_t outside_count8(long long q0, long long head, long long end) {
-    long long a = q0 < head ? head : q0;
-    long long b = q0 + 8 > end ? end : q0 + 8;
-    long long in = b > a ? b - a : 0;
+    const long long a = q0 < head ? head : q0;
+    const long long b = q0 + 8 > end ? end : q0 + 8;
+    const long long in = b > a ? b - a : 0;
     return (uint32_t)(8 - in);
 }
 
@@ -118,6 +121,26 @@ __device__ __forceinline__ uint32_t valid_mask8(long long q0, long long head, lo
     for (int k = 0; k < 8; ++k)
         if (q0 + k >= head && q0 + k < end) m |= 1u << k;
     return m;
+}
+
+__device__ __forceinline__ uint32_t load_chunk_width8(const uint8_t *frame, long long head, long long end,
+                                                      long long q0) {
+    if (q0 >= end) return 0;
+    const u32x4 v = *(const u32x4 *)(frame + 2 * q0);
+    uint32_t d[4] = {v.x, v.y, v.z, v.w};
+    if (q0 < head || q0 + 8 > end)
+        for (int k = 0; k < 4; ++k) d[k] = keep_units(d[k], q0 + 2 * k, head, end);
+    return chunk_width8(d[0], d[1], d[2], d[3]) - outside_count8(q0, head, end);
+}
+
+// Aggregate (bytes) of tile `tl`, computed by one wave from global memory.
+__device__ u64 tile_width8(const uint8_t *frame, long long head, long long end, long long tl) {
+    const uint32_t lane = lane_id();
+    u64 acc = 0;
+    const long long base = tl * kTileUnits;
+    for (int r = 0; r < kTileUnits / kRowUnits; ++r)
+        acc += load_chunk_width8(frame, head, end, base + r * kRowUnits + 8 * (long long)lane);
+    return wave_sum_u64(acc);
 }
 
 // Word j (0..7) of a row, with j = -1 and j = 8 reaching into the halo.
@@ -152,204 +175,174 @@ __device__ __forceinline__ uint32_t encode_word(uint32_t u, uint32_t pv, uint32_
     return (0x80u | ((cp >> 6) & 0x3Fu)) | ((0x80u | (cp & 0x3Fu)) << 8);
 }
 
-template <uint32_t kClass, bool kStore>
-__device__ __forceinline__ u64 encode_lane(const LaneUnits &t, const uint32_t (&off)[kRows],
-                                           const uint32_t (&vm)[kRows], uint8_t *stage8,
-                                           long long wbase, long long head, uint32_t lane) {
-    u64 err = ~0ull;
+// First unpaired surrogate among the lane's words (position << 4 | kind).
+__device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, const uint32_t (&vm)[kRows], long long wbase,
+                                                  long long head, uint32_t lane) {
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t u = word_at(t, r, j);
+            const bool bad = ((vm[r] >> j) & 1u) &&
+                             ((is_high(u) && !is_low(word_at(t, r, j + 1))) || (is_low(u) && !is_high(word_at(t, r, j - 1))));
+            if (bad) {
+                const long long q = wbase + r * kRowUnits + 8 * (long long)lane + j;
+                return ((u64)(q - head) << 4) | (is_high(u) ? kUnpairedHigh : kUnpairedLow);
+            }
+        }
+    }
+    return ~0ull;
+}
+
+template <uint32_t kClass>
+__device__ __forceinline__ void encode_group(const LaneUnits &t, int r0, const uint32_t (&off)[kRows],
+                                             const uint32_t (&vm)[kRows], uint8_t *stage8) {
+#pragma unroll
+    for (int r = r0; r < r0 + kGroup; ++r) {
         uint32_t o = off[r];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (!((vm[r] >> j) & 1u)) continue;
             const uint32_t u = word_at(t, r, j);
-            const uint32_t pv = word_at(t, r, j - 1);
-            const uint32_t nx = word_at(t, r, j + 1);
-            if (kClass == kAnyUnit) {
-                const bool bad = (is_high(u) && !is_low(nx)) || (is_low(u) && !is_high(pv));
-                if (bad && err == ~0ull) {
-                    const long long q = wbase + r * kRowUnits + 8 * (long long)lane + j;
-                    err = ((u64)(q - head) << 4) | (is_high(u) ? kUnpairedHigh : kUnpairedLow);
-                }
-            }
             uint32_t len;
-            const uint32_t b = encode_word<kClass>(u, pv, nx, len);
-            if (kStore) {
-                stage8[o] = (uint8_t)b;
-                if (len > 1) stage8[o + 1] = (uint8_t)(b >> 8);
-                if (len > 2) stage8[o + 2] = (uint8_t)(b >> 16);
-            }
+            const uint32_t b = encode_word<kClass>(u, word_at(t, r, j - 1), word_at(t, r, j + 1), len);
+            stage8[o] = (uint8_t)b;
+            if (len > 1) stage8[o + 1] = (uint8_t)(b >> 8);
+            if (len > 2) stage8[o + 2] = (uint8_t)(b >> 16);
             o += len;
         }
     }
-    return err;
 }
 
-// ASCII rows: keep the low byte of every word.
-__device__ __forceinline__ void narrow_ascii(const LaneUnits &t, const uint32_t (&off)[kRows], uint8_t *stage8) {
+// ASCII rows: keep the low byte of every word.  In an all-ASCII wave the
+// group-local offset of a lane's row is a multiple of 8 bytes.
+__device__ __forceinline__ void narrow_group(const LaneUnits &t, int r0, const uint32_t (&off)[kRows],
+                                             uint8_t *stage8) {
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
+    for (int r = r0; r < r0 + kGroup; ++r) {
         const uint32_t lo = __builtin_amdgcn_perm(t.d[r][1], t.d[r][0], 0x06040200u);
         const uint32_t hi = __builtin_amdgcn_perm(t.d[r][3], t.d[r][2], 0x06040200u);
-        const uint32_t o = off[r];
-        if ((o & 3u) == 0u) {
-            uint32_t *dst = (uint32_t *)(stage8 + o);
-            dst[0] = lo;
-            dst[1] = hi;
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                stage8[o + k] = (uint8_t)(lo >> (8 * k));
-                stage8[o + 4 + k] = (uint8_t)(hi >> (8 * k));
-            }
-        }
+        uint32_t *dst = (uint32_t *)(stage8 + off[r]);
+        dst[0] = lo;
+        dst[1] = hi;
+    }
+}
+
+__device__ __forceinline__ void encode_group_any(uint32_t cls, const LaneUnits &t, int r0,
+                                                 const uint32_t (&off)[kRows], const uint32_t (&vm)[kRows],
+                                                 uint8_t *stage8) {
+    switch (cls) {
+        case kAscii16: narrow_group(t, r0, off, stage8); break;
+        case kUpTo2B: encode_group<kUpTo2B>(t, r0, off, vm, stage8); break;
+        case kBmp: encode_group<kBmp>(t, r0, off, vm, stage8); break;
+        default: encode_group<kAnyUnit>(t, r0, off, vm, stage8); break;
     }
 }
 
 template <bool kConvert>
-__global__ __launch_bounds__(kBlock) void utf16_tile_kernel(
-    const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
-    u64 *__restrict__ status, Ctrl *__restrict__ ctrl, DevResult *__restrict__ result, u64 ntiles) {
-    constexpr int kStageWords = kConvert ? (int)(kStageBytes16 / 4 + 4) : 2;
-    __shared__ uint32_t stage[kStageWords];
+__global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__restrict__ frame, long long head,
+                                                             long long m, uint8_t *__restrict__ out, u64 out_cap,
+                                                             u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
+                                                             u64 ntiles, int spin_limit) {
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords16 : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
-    __shared__ u64 s_tile, s_epoch, s_prefix;
-    __shared__ u64 s_err[kWaves];
+    __shared__ u64 s_prefix;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid >> 6;
-    if (tid == 0) {
-        s_tile = add_agent(&ctrl->ticket, 1ull);
-        s_epoch = ld_agent(&ctrl->epoch);
-    }
-    __syncthreads();
-    const u64 tile = s_tile;
-    const u64 epoch = s_epoch;
+    const u64 tile = blockIdx.x;
     const long long end = head + m;
     const long long wbase = (long long)tile * kTileUnits + (long long)wave * kWaveUnits;
 
     LaneUnits t;
-    load_tile16(frame, head, end, wbase, lane, t);
+    load_span16(frame, head, end, wbase, lane, t);
     uint32_t cls = wave_class16(t);
     if (cls == kAscii16 && (wbase < head || wbase + kWaveUnits > end)) cls = kUpTo2B;
 
-    uint32_t s[kRows], vm[kRows];
+    uint32_t vm[kRows];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
-        vm[r] = valid_mask8(q0, head, end);
-        s[r] = chunk_width8(t.d[r]) - outside_count8(q0, head, end);
-    }
-    uint32_t off[kRows];
-    uint32_t wave_total = 0;
-    {
-        const uint32_t i01 = wave_incl_scan(s[0] | (s[1] << 16), lane);
-        const uint32_t i23 = wave_incl_scan(s[2] | (s[3] << 16), lane);
-        const uint32_t t01 = readlane(i01, kWave - 1), t23 = readlane(i23, kWave - 1);
-        const uint32_t tot[kRows] = {t01 & 0xFFFFu, t01 >> 16, t23 & 0xFFFFu, t23 >> 16};
-        const uint32_t inc[kRows] = {i01 & 0xFFFFu, i01 >> 16, i23 & 0xFFFFu, i23 >> 16};
-        uint32_t base = 0;
+    for (int r = 0; r < kRows; ++r) vm[r] = valid_mask8(wbase + r * kRowUnits + 8 * (long long)lane, head, end);
+
+    u64 err = ~0ull;
+    if (cls == kAnyUnit) err = lane_first_error16(t, vm, wbase, head, lane);
+
+    if (kConvert) {
+        uint32_t s[kRows], off[kRows], rowbase[kRows + 1];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            off[r] = base + inc[r] - s[r];
-            base += tot[r];
+            const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+            s[r] = chunk_width8(t.d[r][0], t.d[r][1], t.d[r][2], t.d[r][3]) - outside_count8(q0, head, end);
         }
-        wave_total = base;
-    }
-    if (lane == 0) s_wave_tot[wave] = wave_total;
-    __syncthreads();
-    uint32_t wave_off = 0, tile_total = 0;
+        rowbase[0] = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        const uint32_t v = s_wave_tot[w];
-        if ((uint32_t)w < wave) wave_off += v;
-        tile_total += v;
-    }
+        for (int p = 0; p < kRows / 2; ++p) {
+            const uint32_t inc = wave_incl_scan(s[2 * p] | (s[2 * p + 1] << 16), lane);
+            const uint32_t tot = readlane(inc, kWave - 1);
+            off[2 * p] = rowbase[2 * p] + (inc & 0xFFFFu) - s[2 * p];
+            rowbase[2 * p + 1] = rowbase[2 * p] + (tot & 0xFFFFu);
+            off[2 * p + 1] = rowbase[2 * p + 1] + (inc >> 16) - s[2 * p + 1];
+            rowbase[2 * p + 2] = rowbase[2 * p + 1] + (tot >> 16);
+        }
+        if (lane == 0) s_wave_tot[wave] = rowbase[kRows];
+        __syncthreads();
+        uint32_t wave_off = 0, tile_total = 0;
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) off[r] += wave_off;
-
-    if (kConvert && wave == 0) {
-        u64 prefix = 0;
-        if (tile == 0) {
-            if (lane == 0) st_agent(status, pack_status(kFlagPrefix, epoch, tile_total));
-        } else {
-            if (lane == 0) st_agent(status + tile, pack_status(kFlagAggregate, epoch, tile_total));
-            prefix = lookback(status, (long long)tile, epoch);
-            if (lane == 0) st_agent(status + tile, pack_status(kFlagPrefix, epoch, prefix + tile_total));
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t v = s_wave_tot[w];
+            if ((uint32_t)w < wave) wave_off += v;
+            tile_total += v;
         }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
+        if (wave == 0) {
+            const u64 epoch = ld_agent(&ctrl->epoch);
+            const u64 prefix = resolve_prefix(status, tile, epoch, spin_limit, tile_total, [=](long long tl) {
+                return tile_width8(frame, head, end, tl);
+            });
+            if (lane == 0) {
+                s_prefix = prefix;
+                if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
+            }
         }
-    }
-
-    uint8_t *stage8 = (uint8_t *)stage;
-    u64 err = ~0ull;
-    switch (cls) {
-        case kAscii16:
-            if (kConvert) narrow_ascii(t, off, stage8);
-            break;
-        case kUpTo2B:
-            encode_lane<kUpTo2B, kConvert>(t, off, vm, stage8, wbase, head, lane);
-            break;
-        case kBmp:
-            encode_lane<kBmp, kConvert>(t, off, vm, stage8, wbase, head, lane);
-            break;
-        default:
-            err = encode_lane<kAnyUnit, kConvert>(t, off, vm, stage8, wbase, head, lane);
-            err = wave_min_u64(err);
-            break;
-    }
-    if (lane == 0) s_err[wave] = err;
-    __syncthreads();
-
-    if (tid == 0) {
-        u64 e = s_err[0];
+        uint8_t *wst8 = (uint8_t *)(stage + wave * kStageWords16);
+        uint32_t gof[kRows];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) e = s_err[w] < e ? s_err[w] : e;
-        if (e != ~0ull) min_agent(&ctrl->err, e);
-    }
-    if (kConvert) {
-        const u64 prefix = s_prefix;
-        u64 nbytes = tile_total;
-        if (prefix >= out_cap) nbytes = 0;
-        else if (prefix + nbytes > out_cap) nbytes = out_cap - prefix;
-        write_out<1>(out + prefix, nbytes, stage, tid);
-    }
-    if (tid == 0 && arrive_last(ctrl, ntiles)) {
-        const u64 e = ld_agent(&ctrl->err);
-        if (e != ~0ull) {
-            write_result(result, (uint32_t)(e & 15u), e >> 4);
-        } else if (kConvert) {
-            const u64 tot = ld_agent(&ctrl->total);
-            write_result(result, tot > out_cap ? kOutputTooSmall : kOk, tot);
-        } else {
-            write_result(result, kOk, (u64)m);
+        for (int r = 0; r < kRows; ++r) gof[r] = off[r] - rowbase[(r / kGroup) * kGroup];
+        encode_group_any(cls, t, 0, gof, vm, wst8);
+        __syncthreads();   // the tile prefix is known
+        const u64 base = s_prefix + wave_off;
+#pragma unroll
+        for (int g = 0; g < kRows / kGroup; ++g) {
+            if (g > 0) encode_group_any(cls, t, g * kGroup, gof, vm, wst8);
+            wave_lds_sync();
+            const u64 b0 = base + rowbase[g * kGroup];
+            u64 nbytes = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
+            if (b0 >= out_cap) nbytes = 0;
+            else if (b0 + nbytes > out_cap) nbytes = out_cap - b0;
+            write_out<1, kWave>(out + b0, nbytes, (const uint32_t *)wst8, lane);
+            wave_lds_sync();
         }
-        reset_ctrl(ctrl);
+    }
+
+    if (cls == kAnyUnit) {
+        err = wave_min_u64(err);
+        if (lane == 0 && err != ~0ull) min_agent(&ctrl->err, err);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void utf8_length_kernel(
-    const uint8_t *__restrict__ frame, long long head, long long m, Ctrl *__restrict__ ctrl,
-    u64 *__restrict__ result, u64 nblocks) {
+__global__ __launch_bounds__(kBlock) void utf8_length_kernel(const uint8_t *__restrict__ frame, long long head,
+                                                              long long m, u64 *__restrict__ partials) {
     __shared__ u64 s_sum[kWaves];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const long long end = head + m;
+    const long long nchunks = (end + 7) / 8;
+    const long long stride = (long long)gridDim.x * kBlock;
     u64 acc = 0;
-    const long long tbase = (long long)blockIdx.x * kTileUnits + (long long)wave * kWaveUnits;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const long long q0 = tbase + r * kRowUnits + 8 * (long long)lane;
-        if (q0 < end) {
-            u32x4 v = __builtin_nontemporal_load((const u32x4 *)(frame + 2 * q0));
-            uint32_t d[4] = {v.x, v.y, v.z, v.w};
-            if (q0 < head || q0 + 8 > end)
-                for (int k = 0; k < 4; ++k) d[k] = keep_units(d[k], q0 + 2 * k, head, end);
-            acc += chunk_width8(d) - outside_count8(q0, head, end);
-        }
+    for (long long c = (long long)blockIdx.x * kBlock + tid; c < nchunks; c += 4 * stride) {
+        uint32_t w0 = load_chunk_width8(frame, head, end, 8 * c);
+        uint32_t w1 = c + stride < nchunks ? load_chunk_width8(frame, head, end, 8 * (c + stride)) : 0;
+        uint32_t w2 = c + 2 * stride < nchunks ? load_chunk_width8(frame, head, end, 8 * (c + 2 * stride)) : 0;
+        uint32_t w3 = c + 3 * stride < nchunks ? load_chunk_width8(frame, head, end, 8 * (c + 3 * stride)) : 0;
+        acc += (u64)w0 + w1 + w2 + w3;
     }
     acc = wave_sum_u64(acc);
     if (lane == 0) s_sum[wave] = acc;
@@ -357,34 +350,36 @@ __global__ __launch_bounds__(kBlock) void utf8_length_kernel(
     if (tid == 0) {
         u64 b = 0;
         for (int w = 0; w < kWaves; ++w) b += s_sum[w];
-        add_agent(&ctrl->total, b);
-        if (arrive_last(ctrl, nblocks)) {
-            *result = ld_agent(&ctrl->total);
-            reset_ctrl(ctrl);
-        }
+        partials[blockIdx.x] = b;
     }
 }
 
-hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
-                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, u64 ntiles,
-                              hipStream_t stream) {
-    if (convert)
-        hipLaunchKernelGGL(utf16_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
-                           head, m, out, out_cap, status, ctrl, result, ntiles);
-    else
-        hipLaunchKernelGGL(utf16_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
-                           head, m, out, out_cap, status, ctrl, result, ntiles);
-    return hipGetLastError();
-}
-
-hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, Ctrl *ctrl, u64 *result,
-                              hipStream_t stream) {
-    const u64 nblocks = (u64)((head + m + kTileUnits - 1) / kTileUnits);
-    hipLaunchKernelGGL(utf8_length_kernel, dim3((unsigned)nblocks), dim3(kBlock), 0, stream, frame, head, m,
-                       ctrl, result, nblocks);
-    return hipGetLastError();
-}
-
 u64 utf16_tiles_for(long long head, long long m) { return (u64)((head + m + kTileUnits - 1) / kTileUnits); }
+
+int partial_blocks(long long units, long long units_per_block);
+
+hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
+                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
+    const u64 ntiles = utf16_tiles_for(head, m);
+    if (convert)
+        hipLaunchKernelGGL(utf16_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head, m,
+                           out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+    else
+        hipLaunchKernelGGL(utf16_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head,
+                           m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(ctrl, result, nullptr, convert ? kFinConvert : kFinValidate, (u64)m, out_cap, nullptr,
+                           0, stream);
+}
+
+hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,
+                              u64 *result, hipStream_t stream) {
+    const int nb = partial_blocks(head + m, 8LL * kBlock * 4);
+    hipLaunchKernelGGL(utf8_length_kernel, dim3(nb), dim3(kBlock), 0, stream, frame, head, m, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(ctrl, nullptr, result, kFinLength, 0, 0, partials, nb, stream);
+}
 
 }  // namespace utfgpu

@@ -18,24 +18,30 @@
 // fires evaluates C exactly (over its positions and the three before).
 // Both facts are checked on the CPU against the oracle by the test suite.
 //
-// Output offsets.  A non-continuation byte emits the character's UTF-16
-// words: width 1, or 2 for a leading byte >= F0 (a surrogate pair).
-// Continuation bytes emit nothing.  Offsets are the exclusive scan of those
-// widths, so every tile knows where its output goes without seeing the
-// characters of other tiles.
+// Output.  A non-continuation byte emits its character's UTF-16 words:
+// width 1, or 2 for a leading byte >= F0 (a surrogate pair); continuation
+// bytes emit nothing.  Offsets are the exclusive scan of those widths, so a
+// tile places its output without seeing other tiles' characters.  A wave
+// converts its span in groups of kGroup rows in two steps: every leading
+// byte stores its four-byte window (itself and the next three bytes) in
+// LDS at its output slot (a four-byte character also stores a marked copy
+// for its low surrogate); then the lanes take aligned 16-byte blocks of the
+// output, decode the eight windows of a block and store it whole.  Decoding
+// work is thus spent per output word, not per input byte.
 #include "device_common.hpp"
 
 namespace utfgpu {
 
-// Words a tile stage holds.  Valid input needs at most one word per byte of
-// the tile plus one: a tile can end with the leading byte of a four-byte
-// character (two words) whose continuation bytes lie in the next tile.
-// Invalid input can announce up to two words per byte; then only the words
-// of the valid prefix (which fit) are kept.
-constexpr uint32_t kStageUnits = kTileBytes + 8;
-
 // Byte class of a wave, over its own bytes and the three bytes before it.
 enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kAny = 3 };
+
+// Slots one wave stages at a time (kGroup rows).  Valid input needs at most
+// one slot per byte of the group plus one: a group can end with the leading
+// byte of a four-byte character (two slots) whose continuation bytes lie
+// beyond it.  Invalid input can announce up to two per byte; then only the
+// slots of the valid prefix (which fit) are kept.
+constexpr uint32_t kStageSlots = kGroup * kRowBytes + 8;
+constexpr int kStageWords = (int)kStageSlots + 4;   // one dword per slot, per wave
 
 // Frame byte q with positions outside [head, end) read as zero.
 __device__ __forceinline__ uint32_t frame_byte(const uint8_t *frame, long long q, long long head, long long end) {
@@ -65,8 +71,8 @@ __device__ uint32_t lead_kind(const uint8_t *frame, long long q, long long head,
 }
 
 // Exact C over frame positions [qlo, qhi): min (position << 4 | kind).
-__device__ __noinline__ u64 exact_scan(const uint8_t *frame, long long head, long long end,
-                                       long long qlo, long long qhi) {
+__device__ __noinline__ u64 exact_scan(const uint8_t *frame, long long head, long long end, long long qlo,
+                                       long long qhi) {
     if (qlo < head) qlo = head;
     if (qhi > end) qhi = end;
     for (long long q = qlo; q < qhi; ++q) {
@@ -93,386 +99,490 @@ __device__ __forceinline__ uint32_t ge_e0(uint32_t x) { return x & (x << 1) & (x
 __device__ __forceinline__ uint32_t ge_f0(uint32_t x) { return x & (x << 1) & (x << 2) & (x << 3); }
 __device__ __forceinline__ uint32_t cont_bits(uint32_t x) { return x & ~(x << 1) & 0x80808080u; }
 
-// Decode the character announced by the non-continuation byte at the low
-// byte of `w4` (w4 holds bytes q..q+3).  Sets `bad` when a value rule (or
-// rule 1) fails; the words are meaningful only for valid characters.
-template <uint32_t kClass>
-__device__ __forceinline__ void decode_char(uint32_t w4, uint32_t &u0, uint32_t &u1, uint32_t &two, bool &bad) {
-    const uint32_t b = w4 & 0xFFu;
-    if (kClass == kUpTo2) {
-        const bool l2 = b >= 0xC0u;
-        const uint32_t cp = l2 ? (((b & 0x1Fu) << 6) | ((w4 >> 8) & 0x3Fu)) : b;
-        bad = l2 && cp < 0x80u;
-        u0 = cp;
-        u1 = 0;
-        two = 0;
-        return;
-    }
-    const uint32_t len = 1u + (b >= 0xC0u) + (b >= 0xE0u) + (b >= 0xF0u);
-    const uint32_t c18 = (((w4 >> 8) & 0x3Fu) << 12) | (((w4 >> 16) & 0x3Fu) << 6) | ((w4 >> 24) & 0x3Fu);
-    const uint32_t lp = b & (0x7Fu >> (len == 1u ? 0u : len));
-    const uint32_t cp = ((lp << 18) | c18) >> (6u * (4u - len));
-    const uint32_t lo = len == 1u ? 0u : (len == 2u ? 0x80u : (len == 3u ? 0x800u : 0x10000u));
-    bad = (b >= 0xF8u) | (cp < lo) | (cp > 0x10FFFFu) | ((cp & 0xFFFFF800u) == 0xD800u);
-    if (kClass == kUpTo3) {
-        u0 = cp;
-        u1 = 0;
-        two = 0;
-    } else {
-        two = len == 4u;
-        u0 = two ? 0xD7C0u + (cp >> 10) : cp;
-        u1 = 0xDC00u | (cp & 0x3FFu);
-    }
+// Bit 7 of each byte of the dword at frame position p that lies outside
+// [head, end).
+__device__ __forceinline__ uint32_t outside_bits(long long p, long long head, long long end) {
+    return ~keep_range(0x80808080u, p, head, end) & 0x80808080u;
 }
 
-// Per-lane view of one tile: the rows of 16 bytes, and the dwords just
-// before and after each row's chunk.
+// Per-lane view of one wave's span: kRows rows of 16 bytes (zero outside
+// the input) and the dwords before the first and after the last chunk of
+// the wave.  `edge` marks a wave that reaches outside the input.
 struct LaneBytes {
     uint32_t d[kRows][4];
-    uint32_t prev[kRows];
-    uint32_t next[kRows];
+    uint32_t hp, hn;
+    bool edge;
 };
 
-__device__ __forceinline__ void load_tile(const uint8_t *frame, long long head, long long end,
-                                          long long wbase, uint32_t lane, LaneBytes &t) {
-    const bool edge_wave = wbase < head || wbase + kWaveBytes > end;
+// Keeps the compiler from merging later recomputations of cheap bit tests
+// with earlier ones (which would keep dozens of values alive in registers).
+__device__ __forceinline__ void fence_values(LaneBytes &t) {
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(t.d[r][k]));
+}
+
+__device__ __forceinline__ uint32_t prev_dword(const LaneBytes &t, int r, uint32_t lane) {
+    const uint32_t p = __shfl_up(t.d[r][3], 1);
+    const uint32_t p0 = r == 0 ? t.hp : readlane(t.d[r - 1][3], kWave - 1);
+    return lane == 0 ? p0 : p;
+}
+__device__ __forceinline__ uint32_t next_dword(const LaneBytes &t, int r, uint32_t lane) {
+    const uint32_t nx = __shfl_down(t.d[r][0], 1);
+    const uint32_t n63 = r == kRows - 1 ? t.hn : readlane(t.d[r + 1][0], 0);
+    return lane == kWave - 1 ? n63 : nx;
+}
+
+// Issue the loads of a wave's span (rows and the two adjacent dwords).
+__device__ __forceinline__ void issue_span(const uint8_t *frame, long long end, long long wbase, uint32_t lane,
+                                           LaneBytes &t) {
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (q0 < end) v = __builtin_nontemporal_load((const u32x4 *)(frame + q0));
         t.d[r][0] = v.x; t.d[r][1] = v.y; t.d[r][2] = v.z; t.d[r][3] = v.w;
-        if (edge_wave && (q0 < head || q0 + 16 > end)) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) t.d[r][k] = keep_range(t.d[r][k], q0 + 4 * k, head, end);
-        }
     }
-    // dwords adjacent to the wave's span
-    uint32_t hp = 0, hn = 0;
-    if (wbase - 4 >= 0 && wbase - 4 < end)
-        hp = keep_range(*(const uint32_t *)(frame + wbase - 4), wbase - 4, head, end);
-    if (wbase + kWaveBytes < end)
-        hn = keep_range(*(const uint32_t *)(frame + wbase + kWaveBytes), wbase + kWaveBytes, head, end);
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        uint32_t p = __shfl_up(t.d[r][3], 1);
-        uint32_t nx = __shfl_down(t.d[r][0], 1);
-        const uint32_t p0 = r == 0 ? hp : readlane(t.d[r - 1][3], kWave - 1);
-        const uint32_t n63 = r == kRows - 1 ? hn : readlane(t.d[r + 1][0], 0);
-        t.prev[r] = lane == 0 ? p0 : p;
-        t.next[r] = lane == kWave - 1 ? n63 : nx;
-    }
+    t.hp = 0;
+    t.hn = 0;
+    if (wbase - 4 >= 0 && wbase - 4 < end) t.hp = *(const uint32_t *)(frame + wbase - 4);
+    if (wbase + kWaveBytes < end) t.hn = *(const uint32_t *)(frame + wbase + kWaveBytes);
 }
 
-__device__ __forceinline__ uint32_t wave_class(const LaneBytes &t, uint32_t lane) {
-    uint32_t a80 = 0, aE0 = 0, aF0 = 0;
+// Zero everything outside [head, end) once the loads have arrived.
+__device__ __forceinline__ void finish_span(long long head, long long end, long long wbase, uint32_t lane,
+                                            LaneBytes &t) {
+    t.hp = keep_range(t.hp, wbase - 4, head, end);
+    t.hn = keep_range(t.hn, wbase + kWaveBytes, head, end);
+    t.edge = wbase < head || wbase + kWaveBytes > end;
+    if (t.edge) {
 #pragma unroll
-    for (int r = 0; r < kRows; ++r)
+        for (int r = 0; r < kRows; ++r) {
+            const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
+            if (q0 < head || q0 + 16 > end) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t x = t.d[r][k];
-            a80 |= x;
-            aE0 |= ge_e0(x);
-            aF0 |= ge_f0(x);
-        }
-    if (lane == 0) {   // the three bytes before the wave
-        const uint32_t h = t.prev[0] & 0xFFFFFF00u;
-        a80 |= h;
-        aE0 |= ge_e0(h);
-        aF0 |= ge_f0(h);
-    }
-    if (__ballot((aF0 & 0x80808080u) != 0)) return kAny;
-    if (__ballot((aE0 & 0x80808080u) != 0)) return kUpTo3;
-    if (__ballot((a80 & 0x80808080u) != 0)) return kUpTo2;
-    return kAscii;
-}
-
-// Cheap detector over the lane's positions (bit 7 of each byte of the
-// result marks must(t) != cont(t)).
-template <uint32_t kClass>
-__device__ __forceinline__ uint32_t mismatch_bits(const LaneBytes &t) {
-    uint32_t mis = 0;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        uint32_t p = t.prev[r];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t x = t.d[r][k];
-            uint32_t must = __builtin_amdgcn_alignbyte(ge_c0(x), ge_c0(p), 3);
-            if (kClass >= kUpTo3) must |= __builtin_amdgcn_alignbyte(ge_e0(x), ge_e0(p), 2);
-            if (kClass >= kAny) must |= __builtin_amdgcn_alignbyte(ge_f0(x), ge_f0(p), 1);
-            mis |= (must & 0x80808080u) ^ cont_bits(x);
-            p = x;
-        }
-    }
-    return mis;
-}
-
-// Output width (UTF-16 words) of one 16-byte chunk: one per non-continuation
-// byte, one more per byte >= F0.  Zero bytes outside the input count one
-// each and are removed by the caller.
-__device__ __forceinline__ uint32_t chunk_width16(const uint32_t (&d)[4]) {
-    uint32_t w = 16;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w = w - __popc(cont_bits(d[k])) + __popc(ge_f0(d[k]) & 0x80808080u);
-    return w;
-}
-
-__device__ __forceinline__ uint32_t outside_count(long long q0, long long head, long long end) {
-    long long a = q0 < head ? head : q0;
-    long long b = q0 + 16 > end ? end : q0 + 16;
-    long long in = b > a ? b - a : 0;
-    return (uint32_t)(16 - in);
-}
-
-// Valid-position mask (bit k: position q0+k is an input byte).
-__device__ __forceinline__ uint32_t valid_mask16(long long q0, long long head, long long end) {
-    if (q0 >= head && q0 + 16 <= end) return 0xFFFFu;
-    uint32_t m = 0;
-    for (int k = 0; k < 16; ++k)
-        if (q0 + k >= head && q0 + k < end) m |= 1u << k;
-    return m;
-}
-
-// Decode a lane's chunks; write words to the tile stage (when kStore) at
-// the tile-local offsets `off[r]`; return whether a value rule failed.
-template <uint32_t kClass, bool kStore>
-__device__ __forceinline__ bool decode_lane(const LaneBytes &t, const uint32_t (&off)[kRows],
-                                            const uint32_t (&vm)[kRows], uint16_t *stage16) {
-    bool anybad = false;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        uint32_t o = off[r];
-        const uint32_t cb[4] = {cont_bits(t.d[r][0]), cont_bits(t.d[r][1]), cont_bits(t.d[r][2]),
-                                cont_bits(t.d[r][3])};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int dw = k >> 2, bk = k & 3;
-            const bool lead = ((cb[dw] >> (8 * bk + 7)) & 1u) == 0u && ((vm[r] >> k) & 1u);
-            if (lead) {
-                const uint32_t lo = t.d[r][dw];
-                const uint32_t hi = dw < 3 ? t.d[r][dw + 1] : t.next[r];
-                const uint32_t w4 = window4(lo, hi, bk);
-                uint32_t u0, u1, two;
-                bool bad;
-                decode_char<kClass>(w4, u0, u1, two, bad);
-                anybad |= bad;
-                if (kStore && o < kStageUnits) {
-                    stage16[o] = (uint16_t)u0;
-                    if (kClass == kAny && two && o + 1 < kStageUnits) stage16[o + 1] = (uint16_t)u1;
-                }
-                o += 1 + (kClass == kAny ? two : 0u);
+                for (int k = 0; k < 4; ++k) t.d[r][k] = keep_range(t.d[r][k], q0 + 4 * k, head, end);
             }
         }
     }
-    return anybad;
 }
 
-// ASCII rows: every byte is one word (zero-extension).
-__device__ __forceinline__ void widen_ascii(const LaneBytes &t, const uint32_t (&off)[kRows], uint16_t *stage16) {
+// Continuation bits of dword k of row r, with positions outside the input
+// marked as continuations (so they neither emit words nor count).
+__device__ __forceinline__ uint32_t lane_cont_bits(const LaneBytes &t, int r, int k, long long wbase,
+                                                   long long head, long long end, uint32_t lane) {
+    uint32_t cb = cont_bits(t.d[r][k]);
+    if (t.edge) cb |= outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end);
+    return cb;
+}
+
+// One pass over the lane's bytes: the wave's byte class (over its bytes
+// and the three before it), each row's output width, and the cheap
+// detector must(t) != cont(t).
+struct Survey {
+    uint32_t cls;
+    bool mis;
+    uint32_t width[kRows];
+};
+
+__device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase, long long head, long long end,
+                                            uint32_t lane, Survey &sv) {
+    uint32_t a80 = lane == 0 ? (t.hp & 0xFFFFFF00u) : 0u;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a80 |= t.d[r][k];
+    if (!__ballot((a80 & 0x80808080u) != 0)) {
+        // all-ASCII wave (the three bytes before it included): one word per byte
+        sv.cls = kAscii;
+        sv.mis = false;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            uint32_t w = 16;
+            if (t.edge)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    w -= __popc(outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end));
+            sv.width[r] = w;
+        }
+        return;
+    }
+    uint32_t aE0 = lane == 0 ? ge_e0(t.hp & 0xFFFFFF00u) : 0u;
+    uint32_t aF0 = lane == 0 ? ge_f0(t.hp & 0xFFFFFF00u) : 0u;
+    uint32_t mis = 0;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
+        const uint32_t p = prev_dword(t, r, lane);
+        uint32_t pc0 = ge_c0(p), pe0 = ge_e0(p), pf0 = ge_f0(p);
+        uint32_t w = 16;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t x = t.d[r][k];
+            const uint32_t c0 = ge_c0(x);
+            const uint32_t e0 = c0 & (x << 2);
+            const uint32_t f0 = e0 & (x << 3);
+            const uint32_t must = __builtin_amdgcn_alignbyte(c0, pc0, 3) | __builtin_amdgcn_alignbyte(e0, pe0, 2) |
+                                  __builtin_amdgcn_alignbyte(f0, pf0, 1);
+            const uint32_t cb = lane_cont_bits(t, r, k, wbase, head, end, lane);
+            mis |= (must & 0x80808080u) ^ cont_bits(x);
+            aE0 |= e0;
+            aF0 |= f0;
+            w = w - __popc(cb) + __popc(f0 & 0x80808080u);
+            pc0 = c0;
+            pe0 = e0;
+            pf0 = f0;
+        }
+        sv.width[r] = w;
+    }
+    sv.mis = mis != 0;
+    sv.cls = __ballot((aF0 & 0x80808080u) != 0) ? kAny : (__ballot((aE0 & 0x80808080u) != 0) ? kUpTo3 : kUpTo2);
+}
+
+// Output width (UTF-16 words) of one 16-byte chunk given its bytes and its
+// continuation bits (positions outside the input marked as continuations):
+// one per non-continuation byte, one more per byte >= F0.
+__device__ __forceinline__ uint32_t chunk_width16(const uint32_t (&d)[4], const uint32_t (&cb)[4]) {
+    uint32_t w = 16;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w = w - __popc(cb[k]) + __popc(ge_f0(d[k]) & 0x80808080u);
+    return w;
+}
+
+// Words of the 16-byte chunk at frame position q0 (loaded from memory).
+__device__ __forceinline__ uint32_t load_chunk_width16(const uint8_t *frame, long long head, long long end,
+                                                       long long q0) {
+    if (q0 >= end) return 0;
+    const u32x4 v = *(const u32x4 *)(frame + q0);
+    uint32_t d[4] = {v.x, v.y, v.z, v.w}, cb[4];
+    const bool edge = q0 < head || q0 + 16 > end;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (edge) d[k] = keep_range(d[k], q0 + 4 * k, head, end);
+        cb[k] = cont_bits(d[k]) | (edge ? outside_bits(q0 + 4 * k, head, end) : 0u);
+    }
+    return chunk_width16(d, cb);
+}
+
+// Aggregate (words) of tile `tl`, computed by one wave from global memory:
+// used when the tile's own workgroup has not published it.
+__device__ __noinline__ u64 tile_width16(const uint8_t *frame, long long head, long long end, long long tl) {
+    const uint32_t lane = lane_id();
+    u64 acc = 0;
+    const long long base = tl * kTileBytes;
+    for (int r = 0; r < kTileBytes / kRowBytes; ++r)
+        acc += load_chunk_width16(frame, head, end, base + r * kRowBytes + 16 * (long long)lane);
+    return wave_sum_u64(acc);
+}
+
+// ------------------------------------------------------------------------
+// Step 1: leading bytes store their windows at their output slots.
+// ------------------------------------------------------------------------
+// The window of a four-byte character's low surrogate is stored with its
+// first byte xor 0x70, which maps F0..F4 into the continuation range 80..84
+// -- a value no leading byte's window starts with.
+template <uint32_t kClass>
+__device__ __forceinline__ void scatter_rows(const LaneBytes &t, int r0, const uint32_t (&gof)[kRows],
+                                             uint32_t *wst, long long wbase, long long head, long long end,
+                                             uint32_t lane) {
+#pragma unroll
+    for (int r = r0; r < r0 + kGroup; ++r) {
+        uint32_t o = gof[r];
+        const uint32_t nx_row = next_dword(t, r, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = t.d[r][j];
+            const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
+            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+            const uint32_t f0 = kClass == kAny ? ge_f0(x) & 0x80808080u : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((lead >> (8 * k + 7)) & 1u) {
+                    const uint32_t win = window4(x, nx, k);
+                    if (o < kStageSlots) wst[o] = win;
+                    if (kClass == kAny && ((f0 >> (8 * k + 7)) & 1u)) {
+                        if (o + 1 < kStageSlots) wst[o + 1] = win ^ 0x70u;
+                        o += 2;
+                    } else {
+                        o += 1;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Step 2: decode windows into UTF-16 words.
+// ------------------------------------------------------------------------
+// Word of the window `w` (low byte = leading byte).  `bad` is set when a
+// value rule (or rule 1) fails for the character; structure (continuation
+// bytes) is checked by the detector.
+template <uint32_t kClass>
+__device__ __forceinline__ uint32_t decode_window(uint32_t w, bool &bad) {
+    if (kClass == kUpTo2) {
+        const uint32_t b0 = w & 0xFFu;
+        const bool l2 = b0 >= 0xC0u;
+        const uint32_t u = l2 ? (((b0 & 0x1Fu) << 6) | ((w >> 8) & 0x3Fu)) : b0;
+        bad |= l2 && u < 0x80u;
+        return u;
+    }
+    bool low = false;
+    if (kClass == kAny) {
+        low = (w & 0xC0u) == 0x80u;
+        if (low) w ^= 0x70u;
+    }
+    const uint32_t b0 = w & 0xFFu;
+    const uint32_t len = 1u + (b0 >= 0xC0u) + (b0 >= 0xE0u) + (kClass == kAny ? (uint32_t)(b0 >= 0xF0u) : 0u);
+    const uint32_t c18 = (((w >> 8) & 0x3Fu) << 12) | (((w >> 16) & 0x3Fu) << 6) | ((w >> 24) & 0x3Fu);
+    const uint32_t lp = b0 & (0x7Fu >> (len == 1u ? 0u : len));
+    const uint32_t cp = ((lp << 18) | c18) >> (6u * (4u - len));
+    const uint32_t lo = len == 1u ? 0u : (len == 2u ? 0x80u : (len == 3u ? 0x800u : 0x10000u));
+    bad |= (cp < lo) | ((cp & 0xFFFFF800u) == 0xD800u);
+    if (kClass == kUpTo3) return cp;
+    bad |= (b0 >= 0xF8u) | (cp > 0x10FFFFu);
+    if (len == 4u) return low ? (0xDC00u | (cp & 0x3FFu)) : (0xD7C0u + (cp >> 10));
+    return cp;
+}
+
+// Decode the group's slots and store words [u0, u0 + nslots) of the output
+// (only those below out_cap are stored; every slot is decoded so the value
+// rules are checked for every character).
+template <uint32_t kClass>
+__device__ __forceinline__ bool decode_store(uint16_t *out, u64 out_cap, u64 u0, uint32_t nslots,
+                                             const uint32_t *wst, uint32_t lane) {
+    bool bad = false;
+    if (nslots > kStageSlots) nslots = kStageSlots;
+    if (nslots == 0) return false;
+    const uintptr_t g0 = (uintptr_t)(out + u0);
+    const uintptr_t g1 = g0 + 2 * (uintptr_t)nslots;
+    const uintptr_t gcap = out_cap > u0 ? g0 + 2 * (uintptr_t)(out_cap - u0) : g0;
+    const uintptr_t c0 = g0 & ~(uintptr_t)15;
+    const uintptr_t cend = (g1 + 15) & ~(uintptr_t)15;
+    for (uintptr_t c = c0 + 16 * (uintptr_t)lane; c < cend; c += 16 * kWave) {
+        if (c >= g0 && c + 16 <= g1) {
+            const uint32_t *w = wst + ((c - g0) >> 1);
+            uint32_t u[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) u[i] = decode_window<kClass>(w[i], bad);
+            if (c + 16 <= gcap) {
+                const u32x4 v = {u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16), u[6] | (u[7] << 16)};
+                __builtin_nontemporal_store(v, (u32x4 *)c);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (c + 2 * i < gcap) *(uint16_t *)(c + 2 * i) = (uint16_t)u[i];
+            }
+        } else {
+            for (uintptr_t a = c; a < c + 16; a += 2) {
+                if (a >= g0 && a < g1) {
+                    const uint32_t v = decode_window<kClass>(wst[(a - g0) >> 1], bad);
+                    if (a < gcap) *(uint16_t *)a = (uint16_t)v;
+                }
+            }
+        }
+    }
+    return bad;
+}
+
+// ASCII groups: widen bytes to words in the stage, then copy them out.
+__device__ __forceinline__ void widen_rows(const LaneBytes &t, int r0, const uint32_t (&gof)[kRows],
+                                           uint32_t *wst) {
+    uint16_t *st16 = (uint16_t *)wst;
+#pragma unroll
+    for (int r = r0; r < r0 + kGroup; ++r) {
         uint32_t w[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             w[2 * k] = __builtin_amdgcn_perm(0u, t.d[r][k], 0x0c010c00u);
             w[2 * k + 1] = __builtin_amdgcn_perm(0u, t.d[r][k], 0x0c030c02u);
         }
-        const uint32_t o = off[r];
-        if (o + 16u > kStageUnits) {
-            // only reachable after invalid bytes earlier in the tile
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (o + 2 * k < kStageUnits) stage16[o + 2 * k] = (uint16_t)(w[k] & 0xFFFFu);
-                if (o + 2 * k + 1 < kStageUnits) stage16[o + 2 * k + 1] = (uint16_t)(w[k] >> 16);
-            }
-        } else if ((o & 7u) == 0u) {
-            u32x4 *dst = (u32x4 *)(stage16 + o);
-            dst[0] = u32x4{w[0], w[1], w[2], w[3]};
-            dst[1] = u32x4{w[4], w[5], w[6], w[7]};
-        } else if ((o & 1u) == 0u) {
-            uint32_t *dst = (uint32_t *)(stage16 + o);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) dst[k] = w[k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                stage16[o + 2 * k] = (uint16_t)(w[k] & 0xFFFFu);
-                stage16[o + 2 * k + 1] = (uint16_t)(w[k] >> 16);
-            }
-        }
+        u32x4 *dst = (u32x4 *)(st16 + gof[r]);   // a multiple of 16 words in an all-ASCII wave
+        dst[0] = u32x4{w[0], w[1], w[2], w[3]};
+        dst[1] = u32x4{w[4], w[5], w[6], w[7]};
     }
 }
 
+// The wave's conversion after the tile prefix is known (group 0 has been
+// staged already).  Returns whether a value rule failed.
+template <uint32_t kClass>
+__device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
+                                             const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
+                                             u64 out_cap, uint32_t *wst, long long wbase, long long head,
+                                             long long end, uint32_t lane) {
+    bool bad = false;
+#pragma unroll
+    for (int g = 0; g < kRows / kGroup; ++g) {
+        if (g > 0) {
+            if (kClass == kAscii) widen_rows(t, g * kGroup, gof, wst);
+            else scatter_rows<kClass>(t, g * kGroup, gof, wst, wbase, head, end, lane);
+        }
+        wave_lds_sync();
+        const u64 u0 = base + rowbase[g * kGroup];
+        const uint32_t nslots = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
+        if (kClass == kAscii) {
+            u64 nunits = nslots;
+            if (u0 >= out_cap) nunits = 0;
+            else if (u0 + nunits > out_cap) nunits = out_cap - u0;
+            write_out<2, kWave>((uint8_t *)(out + u0), 2 * nunits, wst, lane);
+        } else {
+            bad |= decode_store<kClass>(out, out_cap, u0, nslots, wst, lane);
+        }
+        wave_lds_sync();
+    }
+    return bad;
+}
+
+// Validation only: decode every leading byte's window in registers.
+template <uint32_t kClass>
+__device__ __forceinline__ bool check_values(const LaneBytes &t, long long wbase, long long head, long long end,
+                                             uint32_t lane) {
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t nx_row = next_dword(t, r, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = t.d[r][j];
+            const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
+            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((lead >> (8 * k + 7)) & 1u) (void)decode_window<kClass>(window4(x, nx, k), bad);
+        }
+    }
+    return bad;
+}
+
 // ------------------------------------------------------------------------
-// Validation and conversion: one tile per workgroup.
+// Validation and conversion: tile t = workgroup t.
 // ------------------------------------------------------------------------
 template <bool kConvert>
-__global__ __launch_bounds__(kBlock) void utf8_tile_kernel(
-    const uint8_t *__restrict__ frame, long long head, long long n, uint16_t *__restrict__ out,
-    u64 out_cap, u64 *__restrict__ status, Ctrl *__restrict__ ctrl, DevResult *__restrict__ result,
-    u64 ntiles) {
-    constexpr int kStageWords = kConvert ? (kStageUnits / 2 + 4) : 2;   // dwords
-    __shared__ uint32_t stage[kStageWords];
+__global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__restrict__ frame, long long head,
+                                                            long long n, uint16_t *__restrict__ out, u64 out_cap,
+                                                            u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
+                                                            u64 ntiles, int spin_limit) {
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
-    __shared__ u64 s_tile, s_epoch, s_prefix;
-    __shared__ u64 s_err[kWaves];
+    __shared__ u64 s_prefix;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid >> 6;
-    if (tid == 0) {
-        s_tile = add_agent(&ctrl->ticket, 1ull);
-        s_epoch = ld_agent(&ctrl->epoch);
-    }
-    __syncthreads();
-    const u64 tile = s_tile;
-    const u64 epoch = s_epoch;
     const long long end = head + n;
+    const u64 tile = blockIdx.x;
     const long long wbase = (long long)tile * kTileBytes + (long long)wave * kWaveBytes;
-
     LaneBytes t;
-    load_tile(frame, head, end, wbase, lane, t);
-    uint32_t cls = wave_class(t, lane);
-    // the all-ASCII shortcut writes whole chunks: not for waves at the ends
-    if (cls == kAscii && (wbase < head || wbase + kWaveBytes > end)) cls = kUpTo2;
-
-    // widths and in-wave offsets
-    uint32_t s[kRows], vm[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
-        vm[r] = valid_mask16(q0, head, end);
-        s[r] = chunk_width16(t.d[r]) - outside_count(q0, head, end);
-    }
-    uint32_t off[kRows];
-    uint32_t wave_total = 0;
+    issue_span(frame, end, wbase, lane, t);
+    const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
+    finish_span(head, end, wbase, lane, t);
     {
-        const uint32_t i01 = wave_incl_scan(s[0] | (s[1] << 16), lane);
-        const uint32_t i23 = wave_incl_scan(s[2] | (s[3] << 16), lane);
-        const uint32_t t01 = readlane(i01, kWave - 1), t23 = readlane(i23, kWave - 1);
-        const uint32_t tot[kRows] = {t01 & 0xFFFFu, t01 >> 16, t23 & 0xFFFFu, t23 >> 16};
-        const uint32_t inc[kRows] = {i01 & 0xFFFFu, i01 >> 16, i23 & 0xFFFFu, i23 >> 16};
-        uint32_t base = 0;
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            off[r] = base + inc[r] - s[r];
-            base += tot[r];
-        }
-        wave_total = base;
-    }
-    if (lane == 0) s_wave_tot[wave] = wave_total;
-    __syncthreads();
-    uint32_t wave_off = 0, tile_total = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        const uint32_t v = s_wave_tot[w];
-        if ((uint32_t)w < wave) wave_off += v;
-        tile_total += v;
-    }
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) off[r] += wave_off;
+        Survey sv;
+        survey_span(t, wbase, head, end, lane, sv);
+        // the all-ASCII shortcut widens whole chunks: not for waves at the ends
+        const uint32_t cls = (sv.cls == kAscii && t.edge) ? kUpTo2 : sv.cls;
+        bool flag = sv.mis;
+        fence_values(t);
 
-    // publish the tile's aggregate early, then resolve its prefix
-    if (kConvert && wave == 0) {
-        u64 prefix = 0;
-        if (tile == 0) {
-            if (lane == 0) st_agent(status, pack_status(kFlagPrefix, epoch, tile_total));
+        if (kConvert) {
+            // in-wave offsets (row-major) and wave total
+            uint32_t gof[kRows], rowbase[kRows + 1];
+            rowbase[0] = 0;
+#pragma unroll
+            for (int p = 0; p < kRows / 2; ++p) {
+                const uint32_t s0 = sv.width[2 * p], s1 = sv.width[2 * p + 1];
+                const uint32_t inc = wave_incl_scan(s0 | (s1 << 16), lane);
+                const uint32_t tot = readlane(inc, kWave - 1);
+                gof[2 * p] = rowbase[2 * p] + (inc & 0xFFFFu) - s0;
+                rowbase[2 * p + 1] = rowbase[2 * p] + (tot & 0xFFFFu);
+                gof[2 * p + 1] = rowbase[2 * p + 1] + (inc >> 16) - s1;
+                rowbase[2 * p + 2] = rowbase[2 * p + 1] + (tot >> 16);
+            }
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) gof[r] -= rowbase[(r / kGroup) * kGroup];   // offsets inside the group
+            if (lane == 0) s_wave_tot[wave] = rowbase[kRows];
+            __syncthreads();
+            uint32_t wave_off = 0, tile_total = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t v = s_wave_tot[w];
+                if ((uint32_t)w < wave) wave_off += v;
+                tile_total += v;
+            }
+            if (wave == 0) {
+                const u64 prefix = resolve_prefix(status, tile, epoch, spin_limit, tile_total, [=](long long tl) {
+                    return tile_width16(frame, head, end, tl);
+                });
+                if (lane == 0) {
+                    s_prefix = prefix;
+                    if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
+                }
+            }
+            uint32_t *wst = stage + wave * kStageWords;
+            switch (cls) {   // the first group needs no prefix
+                case kAscii: widen_rows(t, 0, gof, wst); break;
+                case kUpTo2: scatter_rows<kUpTo2>(t, 0, gof, wst, wbase, head, end, lane); break;
+                case kUpTo3: scatter_rows<kUpTo3>(t, 0, gof, wst, wbase, head, end, lane); break;
+                default: scatter_rows<kAny>(t, 0, gof, wst, wbase, head, end, lane); break;
+            }
+            __syncthreads();   // the tile prefix is known
+            const u64 base = s_prefix + wave_off;
+            switch (cls) {
+                case kAscii:
+                    convert_wave<kAscii>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    break;
+                case kUpTo2:
+                    flag |= convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    break;
+                case kUpTo3:
+                    flag |= convert_wave<kUpTo3>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    break;
+                default:
+                    flag |= convert_wave<kAny>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    break;
+            }
         } else {
-            if (lane == 0) st_agent(status + tile, pack_status(kFlagAggregate, epoch, tile_total));
-            prefix = lookback(status, (long long)tile, epoch);
-            if (lane == 0) st_agent(status + tile, pack_status(kFlagPrefix, epoch, prefix + tile_total));
+            switch (cls) {
+                case kAscii: break;
+                case kUpTo2: flag = flag || check_values<kUpTo2>(t, wbase, head, end, lane); break;
+                case kUpTo3: flag = flag || check_values<kUpTo3>(t, wbase, head, end, lane); break;
+                default: flag = flag || check_values<kAny>(t, wbase, head, end, lane); break;
+            }
         }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
-        }
-    }
 
-    // decode into the stage, detect errors
-    uint16_t *stage16 = (uint16_t *)stage;
-    bool flag = false;
-    switch (cls) {
-        case kAscii:
-            if (kConvert) widen_ascii(t, off, stage16);
-            break;
-        case kUpTo2:
-            flag = mismatch_bits<kUpTo2>(t) != 0;
-            flag |= decode_lane<kUpTo2, kConvert>(t, off, vm, stage16);
-            break;
-        case kUpTo3:
-            flag = mismatch_bits<kUpTo3>(t) != 0;
-            flag |= decode_lane<kUpTo3, kConvert>(t, off, vm, stage16);
-            break;
-        default:
-            flag = mismatch_bits<kAny>(t) != 0;
-            flag |= decode_lane<kAny, kConvert>(t, off, vm, stage16);
-            break;
-    }
-    u64 err = ~0ull;
-    if (__ballot(flag)) {
-        // exact first error over this lane's positions (and, for the first
-        // lane, the three positions before the wave)
-#pragma unroll 1
-        for (int r = 0; r < kRows; ++r) {
-            const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
-            const long long lo = (r == 0 && lane == 0) ? q0 - 3 : q0;
-            const u64 e = exact_scan(frame, head, end, lo, q0 + 16);
-            if (e < err) err = e;
+        if (__ballot(flag)) {
+            // exact first error over this lane's positions (and, for the first
+            // lane, the three positions before the wave)
+            u64 err = ~0ull;
+            for (int r = 0; r < kRows; ++r) {
+                const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
+                const long long lo = (r == 0 && lane == 0) ? q0 - 3 : q0;
+                const u64 e = exact_scan(frame, head, end, lo, q0 + 16);
+                if (e < err) err = e;
+            }
+            err = wave_min_u64(err);
+            if (lane == 0 && err != ~0ull) min_agent(&ctrl->err, err);
         }
-        err = wave_min_u64(err);
-    }
-    if (lane == 0) s_err[wave] = err;
-    __syncthreads();
-
-    if (tid == 0) {
-        u64 e = s_err[0];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) e = s_err[w] < e ? s_err[w] : e;
-        if (e != ~0ull) min_agent(&ctrl->err, e);
-    }
-    if (kConvert) {
-        const u64 prefix = s_prefix;
-        u64 nunits = tile_total < kStageUnits ? tile_total : kStageUnits;
-        if (prefix >= out_cap) nunits = 0;
-        else if (prefix + nunits > out_cap) nunits = out_cap - prefix;
-        write_out<2>((uint8_t *)(out + prefix), 2 * nunits, stage, tid);
-    }
-    if (tid == 0 && arrive_last(ctrl, ntiles)) {
-        const u64 e = ld_agent(&ctrl->err);
-        if (e != ~0ull) {
-            write_result(result, (uint32_t)(e & 15u), e >> 4);
-        } else if (kConvert) {
-            const u64 tot = ld_agent(&ctrl->total);
-            write_result(result, tot > out_cap ? kOutputTooSmall : kOk, tot);
-        } else {
-            write_result(result, kOk, (u64)n);
-        }
-        reset_ctrl(ctrl);
     }
 }
 
 // ------------------------------------------------------------------------
-// UTF-16 length of UTF-8 (no validation): a plain reduction.
+// UTF-16 length of UTF-8 (no validation): per-workgroup partial sums.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void utf16_length_kernel(
-    const uint8_t *__restrict__ frame, long long head, long long n, Ctrl *__restrict__ ctrl,
-    u64 *__restrict__ result, u64 nblocks) {
+__global__ __launch_bounds__(kBlock) void utf16_length_kernel(const uint8_t *__restrict__ frame, long long head,
+                                                               long long n, u64 *__restrict__ partials) {
     __shared__ u64 s_sum[kWaves];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const long long end = head + n;
+    const long long nchunks = (end + 15) / 16;
+    const long long stride = (long long)gridDim.x * kBlock;
     u64 acc = 0;
-    const long long tbase = (long long)blockIdx.x * kTileBytes + (long long)wave * kWaveBytes;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const long long q0 = tbase + r * kRowBytes + 16 * (long long)lane;
-        if (q0 < end) {
-            u32x4 v = __builtin_nontemporal_load((const u32x4 *)(frame + q0));
-            uint32_t d[4] = {v.x, v.y, v.z, v.w};
-            if (q0 < head || q0 + 16 > end)
-                for (int k = 0; k < 4; ++k) d[k] = keep_range(d[k], q0 + 4 * k, head, end);
-            acc += chunk_width16(d) - outside_count(q0, head, end);
-        }
+    for (long long c = (long long)blockIdx.x * kBlock + tid; c < nchunks; c += 4 * stride) {
+        const uint32_t w0 = load_chunk_width16(frame, head, end, 16 * c);
+        const uint32_t w1 = c + stride < nchunks ? load_chunk_width16(frame, head, end, 16 * (c + stride)) : 0;
+        const uint32_t w2 = c + 2 * stride < nchunks ? load_chunk_width16(frame, head, end, 16 * (c + 2 * stride)) : 0;
+        const uint32_t w3 = c + 3 * stride < nchunks ? load_chunk_width16(frame, head, end, 16 * (c + 3 * stride)) : 0;
+        acc += (u64)w0 + w1 + w2 + w3;
     }
     acc = wave_sum_u64(acc);
     if (lane == 0) s_sum[wave] = acc;
@@ -480,48 +590,107 @@ __global__ __launch_bounds__(kBlock) void utf16_length_kernel(
     if (tid == 0) {
         u64 b = 0;
         for (int w = 0; w < kWaves; ++w) b += s_sum[w];
-        add_agent(&ctrl->total, b);
-        if (arrive_last(ctrl, nblocks)) {
-            *result = ld_agent(&ctrl->total);
-            reset_ctrl(ctrl);
-        }
+        partials[blockIdx.x] = b;
     }
+}
+
+// ------------------------------------------------------------------------
+// Finalize (shared by every kernel family)
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void finalize_kernel(Ctrl *ctrl, DevResult *result, u64 *len_result, int mode,
+                                                           u64 n, u64 out_cap, const u64 *partials, int npartials) {
+    __shared__ u64 s_sum[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    if (mode == kFinLength) {
+        u64 acc = 0;
+        for (int i = (int)tid; i < npartials; i += kBlock) acc += partials[i];
+        acc = wave_sum_u64(acc);
+        if (lane == 0) s_sum[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            u64 b = 0;
+            for (int w = 0; w < kWaves; ++w) b += s_sum[w];
+            *len_result = b;
+        }
+        return;
+    }
+    if (tid != 0) return;
+    const u64 e = ld_agent(&ctrl->err);
+    if (e != ~0ull) {
+        result->status = (int32_t)(e & 15u);
+        result->count = e >> 4;
+    } else if (mode == kFinConvert) {
+        const u64 tot = ld_agent(&ctrl->total);
+        result->status = tot > out_cap ? (int32_t)kOutputTooSmall : (int32_t)kOk;
+        result->count = tot;
+    } else {
+        result->status = kOk;
+        result->count = n;
+    }
+    result->pad = 0;
+    st_agent(&ctrl->err, ~0ull);
+    st_agent(&ctrl->total, 0);
+    st_agent(&ctrl->epoch, ld_agent(&ctrl->epoch) + 1);
+}
+
+// Results of empty inputs for the asynchronous calls (a kernel rather than
+// a copy from host memory, so the call also works under stream capture).
+__global__ void set_result_kernel(DevResult *r, int32_t status, u64 count) {
+    if (threadIdx.x == 0) {
+        r->status = status;
+        r->pad = 0;
+        r->count = count;
+    }
+}
+__global__ void set_u64_kernel(u64 *r, u64 v) {
+    if (threadIdx.x == 0) *r = v;
 }
 
 // ------------------------------------------------------------------------
 // Host-side launchers (C++ linkage, used by the C ABI layer).
 // ------------------------------------------------------------------------
-hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n,
-                             uint16_t *out, u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result,
-                             u64 ntiles, hipStream_t stream) {
+u64 utf8_tiles_for(long long head, long long n) {
+    // three positions past the end belong to tiles too: a leading byte near
+    // the end announces continuation bytes there
+    return (u64)((head + n + 3 + kTileBytes - 1) / kTileBytes);
+}
+
+hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
+                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
+    const u64 ntiles = utf8_tiles_for(head, n);
     if (convert)
-        hipLaunchKernelGGL(utf8_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
-                           head, n, out, out_cap, status, ctrl, result, ntiles);
+        hipLaunchKernelGGL(utf8_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head, n,
+                           out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
     else
-        hipLaunchKernelGGL(utf8_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
-                           head, n, out, out_cap, status, ctrl, result, ntiles);
+        hipLaunchKernelGGL(utf8_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head,
+                           n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(ctrl, result, nullptr, convert ? kFinConvert : kFinValidate, (u64)n, out_cap, nullptr,
+                           0, stream);
+}
+
+int partial_blocks(long long units, long long units_per_block) {
+    long long b = (units + units_per_block - 1) / units_per_block;
+    if (b < 1) b = 1;
+    if (b > kMaxPartials) b = kMaxPartials;
+    return (int)b;
+}
+
+hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, u64 *partials, Ctrl *ctrl,
+                               u64 *result, hipStream_t stream) {
+    const int nb = partial_blocks(head + n, 16LL * kBlock * 4);
+    hipLaunchKernelGGL(utf16_length_kernel, dim3(nb), dim3(kBlock), 0, stream, frame, head, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(ctrl, nullptr, result, kFinLength, 0, 0, partials, nb, stream);
+}
+
+hipError_t launch_finalize(Ctrl *ctrl, DevResult *result, u64 *len_result, int mode, u64 n, u64 out_cap,
+                           const u64 *partials, int npartials, hipStream_t stream) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, stream, ctrl, result, len_result, mode, n,
+                       out_cap, partials, npartials);
     return hipGetLastError();
-}
-
-hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, Ctrl *ctrl, u64 *result,
-                               hipStream_t stream) {
-    const u64 nblocks = (u64)((head + n + kTileBytes - 1) / kTileBytes);
-    hipLaunchKernelGGL(utf16_length_kernel, dim3((unsigned)nblocks), dim3(kBlock), 0, stream, frame, head, n,
-                       ctrl, result, nblocks);
-    return hipGetLastError();
-}
-
-}  // namespace utfgpu
-
-namespace utfgpu {
-
-// Results of empty inputs for the asynchronous calls (a kernel rather than
-// a copy from host memory, so the call also works under stream capture).
-__global__ void set_result_kernel(DevResult *r, int32_t status, u64 count) {
-    if (threadIdx.x == 0) write_result(r, (uint32_t)status, count);
-}
-__global__ void set_u64_kernel(u64 *r, u64 v) {
-    if (threadIdx.x == 0) *r = v;
 }
 
 hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream) {

@@ -1,0 +1,42 @@
+"""The look-back's helping path: with UTFGPU_LOOKBACK_SPINS=0 a wave that
+finds a predecessor's status word missing computes that tile's aggregate
+itself at once.  Run in a child process (the knob is read once per
+process); every result must still match the oracle."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r'''
+import sys
+sys.path.insert(0, ROOT_DIR)
+import numpy as np, torch
+import oracle as O
+import paper_2111_08692_amd as G
+from workloads import make_buffer
+for mix in ("mix1m", "cjk", "emoji", "ascii"):
+    for size in (3 << 20, (5 << 20) + 3):
+        b = make_buffer(mix, size, seed=size % 97).data
+        d = torch.from_numpy(b).to("cuda")
+        st, cnt, out = G.convert_utf8_to_utf16le(d)
+        ost, ocnt, oout = O.convert_utf8_to_utf16le(b)
+        assert (st, cnt) == (ost, ocnt), (mix, size)
+        assert np.array_equal(out[:cnt].cpu().numpy().view(np.uint16), oout[:ocnt]), (mix, size)
+        u = torch.from_numpy(oout[:ocnt].view(np.int16)).to("cuda")
+        st, cnt, back = G.convert_utf16le_to_utf8(u)
+        assert (st, cnt) == (0, b.size) and np.array_equal(back[:cnt].cpu().numpy(), b), (mix, size)
+print("helping path ok", flush=True)
+'''
+
+
+def test_helping_path_matches_oracle():
+    env = dict(os.environ, UTFGPU_LOOKBACK_SPINS="0")
+    r = subprocess.run([sys.executable, "-c", "ROOT_DIR = " + repr(ROOT) + "\n" + CHILD], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "helping path ok" in r.stdout
