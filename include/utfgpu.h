@@ -169,6 +169,11 @@ int32_t utfgpu_release_workspace(void);
 /* Library version string, e.g. "utfgpu 0.1 gfx950". */
 const char *utfgpu_version(void);
 
+/* Input bytes one workgroup of the validate/convert kernels covers (a tile
+ * of UTF-8 bytes, or of UTF-16LE bytes: half as many words).  Informational:
+ * tests use it to place inputs across tile boundaries.  Needs no GPU. */
+uint64_t utfgpu_tile_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif

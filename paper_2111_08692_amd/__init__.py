@@ -55,7 +55,7 @@ EXPORTS = (
     "convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "validate_utf16le_async", "utf16_length_from_utf8_async",
     "utf8_length_from_utf16le_async", "convert_utf8_to_utf16le_async",
-    "convert_utf16le_to_utf8_async", "utfgpu_release_workspace", "utfgpu_version",
+    "convert_utf16le_to_utf8_async", "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
 )
 
 
@@ -80,6 +80,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "convert_utf16le_to_utf8_async": ([P, U64, P, U64, P, P], I32),
         "utfgpu_release_workspace": ([], I32),
         "utfgpu_version": ([], ctypes.c_char_p),
+        "utfgpu_tile_bytes": ([], U64),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -109,6 +110,11 @@ def load() -> ctypes.CDLL:
 
 def version() -> str:
     return load().utfgpu_version().decode()
+
+
+def tile_bytes() -> int:
+    """Input bytes one workgroup of the validate/convert kernels covers."""
+    return int(load().utfgpu_tile_bytes())
 
 
 def release_workspace() -> int:

@@ -376,4 +376,6 @@ int32_t utfgpu_release_workspace(void) {
 
 const char *utfgpu_version(void) { return "utfgpu 0.1 gfx950"; }
 
+uint64_t utfgpu_tile_bytes(void) { return (uint64_t)utfgpu::kTileBytes; }
+
 }  // extern "C"

@@ -31,17 +31,18 @@
 
 namespace utfgpu {
 
-// Tiles of 64 KiB: the decoupled look-back costs one status round trip
-// per tile, which smaller tiles cannot hide at full HBM bandwidth.
+// Tiles of 32 KiB in workgroups of eight waves: two workgroups fit on a
+// CU (at up to 128 VGPRs), so one's load latency and look-back wait
+// overlap the other's work.
 constexpr int kWave = 64;
-constexpr int kWaves = 16;
-constexpr int kBlock = kWaves * kWave;             // 1024 lanes
+constexpr int kWaves = 8;
+constexpr int kBlock = kWaves * kWave;             // 512 lanes
 constexpr int kRows = 4;
 constexpr int kGroup = 1;                          // rows staged at a time
 constexpr int kChunk = 16;
 constexpr int kRowBytes = kWave * kChunk;          // 1024
 constexpr int kWaveBytes = kRows * kRowBytes;      // 4096
-constexpr int kTileBytes = kWaves * kWaveBytes;    // 65536
+constexpr int kTileBytes = kWaves * kWaveBytes;    // 32768
 constexpr int kMaxPartials = 2048;                 // workgroups of the length reductions
 
 // Status codes; the same values as the public header.
@@ -274,6 +275,36 @@ __device__ __forceinline__ void write_out(uint8_t *g0p, u64 nbytes, const uint32
                         *(uint16_t *)a = *(const uint16_t *)(sb + so);
                     else
                         *(uint8_t *)a = sb[so];
+                }
+            }
+        }
+    }
+}
+
+// Same, for a stage laid out by 16-byte blocks of global memory: global
+// byte g sits at stage byte g - (g0 & ~15), so the data starts at stage
+// byte g0 & 15 and every whole block is one aligned 16-byte LDS read.
+template <int kUnit, int kThreads>
+__device__ __forceinline__ void write_out_aligned(uint8_t *g0p, u64 nbytes, const uint32_t *stage, uint32_t tid) {
+    if (nbytes == 0) return;
+    const uintptr_t g0 = (uintptr_t)g0p;
+    const uintptr_t g1 = g0 + nbytes;
+    const uintptr_t c0 = g0 & ~(uintptr_t)15;
+    const uintptr_t cend = (g1 + 15) & ~(uintptr_t)15;
+    const uint8_t *sb = (const uint8_t *)stage;
+    for (uintptr_t c = c0 + 16 * (uintptr_t)tid; c < cend; c += 16 * kThreads) {
+        const uint32_t so = (uint32_t)(c - c0);
+        if (c >= g0 && c + 16 <= g1) {
+            const u32x4 v = *(const u32x4 *)(sb + so);
+            __builtin_nontemporal_store(v, (u32x4 *)c);
+        } else {
+            for (uint32_t k = 0; k < 16; k += kUnit) {
+                const uintptr_t a = c + k;
+                if (a >= g0 && a < g1) {
+                    if (kUnit == 2)
+                        *(uint16_t *)a = *(const uint16_t *)(sb + so + k);
+                    else
+                        *(uint8_t *)a = sb[so + k];
                 }
             }
         }

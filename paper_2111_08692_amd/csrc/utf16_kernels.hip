@@ -15,16 +15,25 @@
 // The first error is the smallest word that is a high surrogate not
 // followed by a low one, or a low surrogate not preceded by a high one; it
 // depends only on the word and its two neighbours.
+//
+// Output.  A wave converts one row at a time into its LDS stage, laid out
+// by 16-byte blocks of the output (the row's first byte at stage byte
+// out & 15), then copies whole blocks out with aligned 16-byte stores.
+// Every word stores three bytes at its offset, in word order, so the bytes
+// past a shorter encoding are overwritten by the next word of the lane;
+// only the first two bytes of a lane can keep stray bytes (from the
+// previous lane's last word), and the lane rewrites them at the end.
 #include "device_common.hpp"
 
 namespace utfgpu {
 
-constexpr int kRowUnits = kRowBytes / 2;       // 512
+constexpr int kRowUnits = kRowBytes / 2;       // 512 words per row
 constexpr int kWaveUnits = kWaveBytes / 2;     // 2048 words per wave
 constexpr int kTileUnits = kTileBytes / 2;     // 32768 words per tile
-// bytes one wave stages at a time: at most 3 per word
-constexpr uint32_t kStageBytes = 3u * kGroup * kRowUnits;
-constexpr int kStageWords16 = (int)kStageBytes / 4 + 4;
+// one row of output (at most 3 bytes per word) shifted by up to 15 bytes,
+// plus the stray bytes past its end
+constexpr int kStageBytes16 = 3 * kRowUnits + 32;
+constexpr int kStageWords16 = kStageBytes16 / 4;   // a multiple of 4: stages stay 16-byte aligned
 
 enum : uint32_t { kAscii16 = 0, kUpTo2B = 1, kBmp = 2, kAnyUnit = 3 };
 
@@ -36,66 +45,56 @@ __device__ __forceinline__ uint32_t keep_units(uint32_t x, long long p, long lon
     return x & ((k0 ? 0x0000FFFFu : 0u) | (k1 ? 0xFFFF0000u : 0u));
 }
 
+// Per-lane view of one wave's span: kRows rows of eight words (zero
+// outside the input), the dword before the wave (its high word is the word
+// before) and the dword after it (its low word is the word after).
 struct LaneUnits {
-    uint32_t d[kRows][4];   // eight words per row, two per dword (low half first)
-    uint32_t prev[kRows];   // dword before the chunk (its high half is the word before)
-    uint32_t next[kRows];   // dword after the chunk (its low half is the word after)
+    uint32_t d[kRows][4];
+    uint32_t hp, hn;
+    bool edge;
 };
 
 __device__ __forceinline__ void load_span16(const uint8_t *frame, long long head, long long end, long long wbase,
                                             uint32_t lane, LaneUnits &t) {
-    const bool edge_wave = wbase < head || wbase + kWaveUnits > end;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (q0 < end) v = __builtin_nontemporal_load((const u32x4 *)(frame + 2 * q0));
         t.d[r][0] = v.x; t.d[r][1] = v.y; t.d[r][2] = v.z; t.d[r][3] = v.w;
-        if (edge_wave && (q0 < head || q0 + 8 > end)) {
+    }
+    t.hp = 0;
+    t.hn = 0;
+    if (wbase - 2 >= 0 && wbase - 2 < end) t.hp = *(const uint32_t *)(frame + 2 * (wbase - 2));
+    if (wbase + kWaveUnits < end) t.hn = *(const uint32_t *)(frame + 2 * (wbase + kWaveUnits));
+    t.hp = keep_units(t.hp, wbase - 2, head, end);
+    t.hn = keep_units(t.hn, wbase + kWaveUnits, head, end);
+    t.edge = wbase < head || wbase + kWaveUnits > end;
+    if (t.edge) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
 #pragma unroll
             for (int k = 0; k < 4; ++k) t.d[r][k] = keep_units(t.d[r][k], q0 + 2 * k, head, end);
         }
     }
-    uint32_t hp = 0, hn = 0;
-    if (wbase - 2 >= 0 && wbase - 2 < end)
-        hp = keep_units(*(const uint32_t *)(frame + 2 * (wbase - 2)), wbase - 2, head, end);
-    if (wbase + kWaveUnits < end)
-        hn = keep_units(*(const uint32_t *)(frame + 2 * (wbase + kWaveUnits)), wbase + kWaveUnits, head, end);
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const uint32_t p = __shfl_up(t.d[r][3], 1);
-        const uint32_t nx = __shfl_down(t.d[r][0], 1);
-        const uint32_t p0 = r == 0 ? hp : readlane(t.d[r - 1][3], kWave - 1);
-        const uint32_t n63 = r == kRows - 1 ? hn : readlane(t.d[r + 1][0], 0);
-        t.prev[r] = lane == 0 ? p0 : p;
-        t.next[r] = lane == kWave - 1 ? n63 : nx;
-    }
+}
+
+// The word before / after the lane's chunk of row r.
+__device__ __forceinline__ uint32_t prev_word(const LaneUnits &t, int r, uint32_t lane) {
+    const uint32_t p = __shfl_up(t.d[r][3], 1);
+    const uint32_t p0 = r == 0 ? t.hp : readlane(t.d[r - 1][3], kWave - 1);
+    return (lane == 0 ? p0 : p) >> 16;
+}
+__device__ __forceinline__ uint32_t next_word(const LaneUnits &t, int r, uint32_t lane) {
+    const uint32_t nx = __shfl_down(t.d[r][0], 1);
+    const uint32_t n63 = r == kRows - 1 ? t.hn : readlane(t.d[r + 1][0], 0);
+    return (lane == kWave - 1 ? n63 : nx) & 0xFFFFu;
 }
 
 __device__ __forceinline__ bool is_sur(uint32_t u) { return (u & 0xF800u) == 0xD800u; }
 __device__ __forceinline__ bool is_high(uint32_t u) { return (u & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low(uint32_t u) { return (u & 0xFC00u) == 0xDC00u; }
-
-// Any surrogate among the two words of x.
-__device__ __forceinline__ bool has_sur(uint32_t x) { return is_sur(x & 0xFFFFu) || is_sur(x >> 16); }
-
-__device__ __forceinline__ uint32_t wave_class16(const LaneUnits &t) {
-    uint32_t a80 = 0, a800 = 0;
-    bool sur = false;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t x = t.d[r][k];
-            a80 |= x & 0xFF80FF80u;
-            a800 |= x & 0xF800F800u;
-            sur = sur || has_sur(x);
-        }
-    if (__ballot(sur)) return kAnyUnit;
-    if (__ballot(a800 != 0)) return kBmp;
-    if (__ballot(a80 != 0)) return kUpTo2B;
-    return kAscii16;
-}
 
 // UTF-8 bytes of one word (1 below 0x80, 2 below 0x800, 2 per surrogate
 // word, 3 otherwise).
@@ -108,19 +107,12 @@ __device__ __forceinline__ uint32_t chunk_width8(uint32_t d0, uint32_t d1, uint3
            width8(d2 & 0xFFFFu) + width8(d2 >> 16) + width8(d3 & 0xFFFFu) + width8(d3 >> 16);
 }
 
+// Words of the chunk at frame word q0 that lie outside [head, end).
 __device__ __forceinline__ uint32_t outside_count8(long long q0, long long head, long long end) {
     const long long a = q0 < head ? head : q0;
     const long long b = q0 + 8 > end ? end : q0 + 8;
     const long long in = b > a ? b - a : 0;
     return (uint32_t)(8 - in);
-}
-
-__device__ __forceinline__ uint32_t valid_mask8(long long q0, long long head, long long end) {
-    if (q0 >= head && q0 + 8 <= end) return 0xFFu;
-    uint32_t m = 0;
-    for (int k = 0; k < 8; ++k)
-        if (q0 + k >= head && q0 + k < end) m |= 1u << k;
-    return m;
 }
 
 __device__ __forceinline__ uint32_t load_chunk_width8(const uint8_t *frame, long long head, long long end,
@@ -133,8 +125,9 @@ __device__ __forceinline__ uint32_t load_chunk_width8(const uint8_t *frame, long
     return chunk_width8(d[0], d[1], d[2], d[3]) - outside_count8(q0, head, end);
 }
 
-// Aggregate (bytes) of tile `tl`, computed by one wave from global memory.
-__device__ u64 tile_width8(const uint8_t *frame, long long head, long long end, long long tl) {
+// Aggregate (bytes) of tile `tl`, computed by one wave from global memory:
+// used when the tile's own workgroup has not published it.
+__device__ __noinline__ u64 tile_width8(const uint8_t *frame, long long head, long long end, long long tl) {
     const uint32_t lane = lane_id();
     u64 acc = 0;
     const long long base = tl * kTileUnits;
@@ -143,99 +136,176 @@ __device__ u64 tile_width8(const uint8_t *frame, long long head, long long end, 
     return wave_sum_u64(acc);
 }
 
-// Word j (0..7) of a row, with j = -1 and j = 8 reaching into the halo.
-__device__ __forceinline__ uint32_t word_at(const LaneUnits &t, int r, int j) {
-    if (j < 0) return t.prev[r] >> 16;
-    if (j > 7) return t.next[r] & 0xFFFFu;
-    return (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-}
-
-// UTF-8 bytes of word u (packed, first byte lowest) and their number.
-// `pv` and `nx` are the words before and after (used by surrogates).
-template <uint32_t kClass>
-__device__ __forceinline__ uint32_t encode_word(uint32_t u, uint32_t pv, uint32_t nx, uint32_t &len) {
-    if (u < 0x80u) {
-        len = 1;
-        return u;
+// Wave class and the output width (bytes) of each of the lane's rows.
+template <bool kWidths>
+__device__ __forceinline__ uint32_t survey16(const LaneUnits &t, long long wbase, long long head, long long end,
+                                             uint32_t lane, uint32_t (&width)[kRows]) {
+    uint32_t a80 = 0, a800 = 0;
+    bool sur = false;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t x = t.d[r][k];
+            a80 |= x & 0xFF80FF80u;
+            a800 |= x & 0xF800F800u;
+            sur = sur || is_sur(x & 0xFFFFu) || is_sur(x >> 16);
+        }
+    uint32_t cls = kAscii16;
+    if (__ballot(sur)) cls = kAnyUnit;
+    else if (__ballot(a800 != 0)) cls = kBmp;
+    else if (__ballot(a80 != 0)) cls = kUpTo2B;
+    if (!kWidths) return cls;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        uint32_t w = 8;
+        if (cls != kAscii16) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t u0 = t.d[r][k] & 0xFFFFu, u1 = t.d[r][k] >> 16;
+                w += (u0 >= 0x80u) + (u1 >= 0x80u);
+                if (cls >= kBmp) w += (u0 >= 0x800u) + (u1 >= 0x800u);
+                if (cls == kAnyUnit) w -= (uint32_t)is_sur(u0) + (uint32_t)is_sur(u1);
+            }
+        }
+        if (t.edge) w -= outside_count8(wbase + r * kRowUnits + 8 * (long long)lane, head, end);
+        width[r] = w;
     }
-    if (kClass == kUpTo2B || u < 0x800u) {
-        len = 2;
-        return (0xC0u | (u >> 6)) | ((0x80u | (u & 0x3Fu)) << 8);
-    }
-    if (kClass == kBmp || !is_sur(u)) {
-        len = 3;
-        return (0xE0u | (u >> 12)) | ((0x80u | ((u >> 6) & 0x3Fu)) << 8) | ((0x80u | (u & 0x3Fu)) << 16);
-    }
-    len = 2;
-    if (is_high(u)) {
-        const uint32_t cp = 0x10000u + (((u & 0x3FFu) << 10) | (nx & 0x3FFu));
-        return (0xF0u | (cp >> 18)) | ((0x80u | ((cp >> 12) & 0x3Fu)) << 8);
-    }
-    const uint32_t cp = 0x10000u + (((pv & 0x3FFu) << 10) | (u & 0x3FFu));
-    return (0x80u | ((cp >> 6) & 0x3Fu)) | ((0x80u | (cp & 0x3Fu)) << 8);
+    return cls;
 }
 
 // First unpaired surrogate among the lane's words (position << 4 | kind).
-__device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, const uint32_t (&vm)[kRows], long long wbase,
-                                                  long long head, uint32_t lane) {
+__device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, long long wbase, long long head,
+                                                  long long end, uint32_t lane) {
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
+        uint32_t u[10];
+        u[0] = prev_word(t, r, lane);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t u = word_at(t, r, j);
-            const bool bad = ((vm[r] >> j) & 1u) &&
-                             ((is_high(u) && !is_low(word_at(t, r, j + 1))) || (is_low(u) && !is_high(word_at(t, r, j - 1))));
-            if (bad) {
-                const long long q = wbase + r * kRowUnits + 8 * (long long)lane + j;
-                return ((u64)(q - head) << 4) | (is_high(u) ? kUnpairedHigh : kUnpairedLow);
-            }
+        for (int j = 0; j < 8; ++j) u[j + 1] = (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+        u[9] = next_word(t, r, lane);
+        u64 err = ~0ull;
+#pragma unroll
+        for (int j = 7; j >= 0; --j) {   // backwards: the smallest position is kept
+            const long long q = wbase + r * kRowUnits + 8 * (long long)lane + j;
+            const uint32_t w = u[j + 1];
+            const bool bad_hi = is_high(w) && !is_low(u[j + 2]);
+            const bool bad_lo = is_low(w) && !is_high(u[j]);
+            if ((bad_hi || bad_lo) && q >= head && q < end)
+                err = ((u64)(q - head) << 4) | (bad_hi ? kUnpairedHigh : kUnpairedLow);
         }
+        if (err != ~0ull) return err;
     }
     return ~0ull;
 }
 
+// UTF-8 bytes of word u (first byte lowest) and their number; `pv` and
+// `nx` are the words before and after (used by surrogates).  No branches.
 template <uint32_t kClass>
-__device__ __forceinline__ void encode_group(const LaneUnits &t, int r0, const uint32_t (&off)[kRows],
-                                             const uint32_t (&vm)[kRows], uint8_t *stage8) {
+__device__ __forceinline__ uint32_t encode_word(uint32_t u, uint32_t pv, uint32_t nx, uint32_t &len) {
+    const uint32_t c1 = u >= 0x80u, c2 = u >= 0x800u;
+    const uint32_t t0 = 0x80u | (u & 0x3Fu);
+    uint32_t e2 = (0xC0u | (u >> 6)) | (t0 << 8);
+    if (kClass == kUpTo2B) {
+        len = 1u + c1;
+        return c1 ? e2 : u;
+    }
+    uint32_t e3 = (0xE0u | (u >> 12)) | ((0x80u | ((u >> 6) & 0x3Fu)) << 8) | (t0 << 16);
+    asm volatile("" : "+v"(e2), "+v"(e3));   // selects, not branches
+    const uint32_t e = c2 ? e3 : (c1 ? e2 : u);
+    if (kClass == kBmp) {
+        len = 1u + c1 + c2;
+        return e;
+    }
+    // surrogates: the high word writes F0|.., 80|.. of the pair's code
+    // point, the low word the last two bytes
+    const bool hi = is_high(u), sur = is_sur(u);
+    const uint32_t cp = 0x10000u + ((((hi ? u : pv) & 0x3FFu) << 10) | ((hi ? nx : u) & 0x3FFu));
+    uint32_t sh = (0xF0u | (cp >> 18)) | ((0x80u | ((cp >> 12) & 0x3Fu)) << 8);
+    uint32_t sl = (0x80u | ((cp >> 6) & 0x3Fu)) | ((0x80u | (cp & 0x3Fu)) << 8);
+    asm volatile("" : "+v"(sh), "+v"(sl));
+    len = sur ? 2u : 1u + c1 + c2;
+    return sur ? (hi ? sh : sl) : e;
+}
+
+// Word j of the lane's chunk of row r, with j = -1 and j = 8 the words
+// before and after it.
+__device__ __forceinline__ uint32_t word_of(const LaneUnits &t, int r, int j, uint32_t pv, uint32_t nx) {
+    if (j < 0) return pv;
+    if (j > 7) return nx;
+    return (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+}
+
+// Encode the lane's chunk of row r into the stage at byte offset o, then
+// rewrite the lane's first two bytes.
+template <uint32_t kClass>
+__device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o, uint8_t *st, long long wbase,
+                                           long long head, long long end, uint32_t lane) {
+    const uint32_t pv = kClass == kAnyUnit ? prev_word(t, r, lane) : 0u;
+    const uint32_t nx = kClass == kAnyUnit ? next_word(t, r, lane) : 0u;
+    const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+    const uint32_t o0 = o;
+    uint32_t e0 = 0, e1 = 0, l0 = 0;
 #pragma unroll
-    for (int r = r0; r < r0 + kGroup; ++r) {
-        uint32_t o = off[r];
+    for (int j = 0; j < 8; ++j) {
+        uint32_t len;
+        const uint32_t e = encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx),
+                                               word_of(t, r, j + 1, pv, nx), len);
+        if (t.edge && (q0 + j < head || q0 + j >= end)) len = 0;
+        st[o] = (uint8_t)e;
+        st[o + 1] = (uint8_t)(e >> 8);
+        st[o + 2] = (uint8_t)(e >> 16);
+        if (j == 0) {
+            e0 = e;
+            l0 = len;
+        }
+        if (j == 1) e1 = e;
+        o += len;
+    }
+    wave_lds_sync();   // every lane's stores land before the rewrite
+    uint32_t first, nfirst;
+    if (!t.edge) {
+        first = l0 >= 2u ? (e0 & 0xFFFFu) : ((e0 & 0xFFu) | ((e1 & 0xFFu) << 8));
+        nfirst = 2;
+    } else {
+        first = 0;
+        nfirst = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            if (!((vm[r] >> j) & 1u)) continue;
-            const uint32_t u = word_at(t, r, j);
             uint32_t len;
-            const uint32_t b = encode_word<kClass>(u, word_at(t, r, j - 1), word_at(t, r, j + 1), len);
-            stage8[o] = (uint8_t)b;
-            if (len > 1) stage8[o + 1] = (uint8_t)(b >> 8);
-            if (len > 2) stage8[o + 2] = (uint8_t)(b >> 16);
-            o += len;
+            const uint32_t e = encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx),
+                                                   word_of(t, r, j + 1, pv, nx), len);
+            if (q0 + j < head || q0 + j >= end) len = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if ((uint32_t)k < len && nfirst < 2u) {
+                    first |= ((e >> (8 * k)) & 0xFFu) << (8 * nfirst);
+                    ++nfirst;
+                }
+            }
         }
     }
+    if (nfirst >= 1u) st[o0] = (uint8_t)first;
+    if (nfirst >= 2u) st[o0 + 1] = (uint8_t)(first >> 8);
 }
 
-// ASCII rows: keep the low byte of every word.  In an all-ASCII wave the
-// group-local offset of a lane's row is a multiple of 8 bytes.
-__device__ __forceinline__ void narrow_group(const LaneUnits &t, int r0, const uint32_t (&off)[kRows],
-                                             uint8_t *stage8) {
-#pragma unroll
-    for (int r = r0; r < r0 + kGroup; ++r) {
-        const uint32_t lo = __builtin_amdgcn_perm(t.d[r][1], t.d[r][0], 0x06040200u);
-        const uint32_t hi = __builtin_amdgcn_perm(t.d[r][3], t.d[r][2], 0x06040200u);
-        uint32_t *dst = (uint32_t *)(stage8 + off[r]);
+// All-ASCII rows: the low byte of every word.  With the row's first byte at
+// stage byte s = 4a + b, lane L owns row bytes [8L, 8L+8) and stores the
+// aligned stage dwords 2L + a and 2L + a + 1, which hold row bytes
+// [8L - b, 8L - b + 8) (the last b of them from the previous lane).
+__device__ __forceinline__ void narrow_row(const LaneUnits &t, int r, uint32_t s, uint32_t *st, uint32_t lane) {
+    const uint32_t lo = __builtin_amdgcn_perm(t.d[r][1], t.d[r][0], 0x06040200u);
+    const uint32_t hi = __builtin_amdgcn_perm(t.d[r][3], t.d[r][2], 0x06040200u);
+    const uint32_t a = s >> 2, b = s & 3u;
+    const uint32_t ph = __shfl_up(hi, 1);
+    uint32_t *dst = st + 2 * lane + a;
+    if (b == 0) {
         dst[0] = lo;
         dst[1] = hi;
-    }
-}
-
-__device__ __forceinline__ void encode_group_any(uint32_t cls, const LaneUnits &t, int r0,
-                                                 const uint32_t (&off)[kRows], const uint32_t (&vm)[kRows],
-                                                 uint8_t *stage8) {
-    switch (cls) {
-        case kAscii16: narrow_group(t, r0, off, stage8); break;
-        case kUpTo2B: encode_group<kUpTo2B>(t, r0, off, vm, stage8); break;
-        case kBmp: encode_group<kBmp>(t, r0, off, vm, stage8); break;
-        default: encode_group<kAnyUnit>(t, r0, off, vm, stage8); break;
+    } else {
+        dst[0] = __builtin_amdgcn_alignbyte(lo, ph, 4 - b);
+        dst[1] = __builtin_amdgcn_alignbyte(hi, lo, 4 - b);
+        if (lane == kWave - 1) dst[2] = __builtin_amdgcn_alignbyte(0u, hi, 4 - b);
     }
 }
 
@@ -257,31 +327,22 @@ __global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__res
 
     LaneUnits t;
     load_span16(frame, head, end, wbase, lane, t);
-    uint32_t cls = wave_class16(t);
-    if (cls == kAscii16 && (wbase < head || wbase + kWaveUnits > end)) cls = kUpTo2B;
-
-    uint32_t vm[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) vm[r] = valid_mask8(wbase + r * kRowUnits + 8 * (long long)lane, head, end);
-
-    u64 err = ~0ull;
-    if (cls == kAnyUnit) err = lane_first_error16(t, vm, wbase, head, lane);
+    const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
+    uint32_t width[kRows];
+    uint32_t cls = survey16<kConvert>(t, wbase, head, end, lane, width);
+    if (cls == kAscii16 && t.edge) cls = kUpTo2B;   // whole-chunk narrowing: not at the ends
 
     if (kConvert) {
-        uint32_t s[kRows], off[kRows], rowbase[kRows + 1];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
-            s[r] = chunk_width8(t.d[r][0], t.d[r][1], t.d[r][2], t.d[r][3]) - outside_count8(q0, head, end);
-        }
+        uint32_t off[kRows], rowbase[kRows + 1];
         rowbase[0] = 0;
 #pragma unroll
         for (int p = 0; p < kRows / 2; ++p) {
-            const uint32_t inc = wave_incl_scan(s[2 * p] | (s[2 * p + 1] << 16), lane);
+            const uint32_t s0 = width[2 * p], s1 = width[2 * p + 1];
+            const uint32_t inc = wave_incl_scan(s0 | (s1 << 16), lane);
             const uint32_t tot = readlane(inc, kWave - 1);
-            off[2 * p] = rowbase[2 * p] + (inc & 0xFFFFu) - s[2 * p];
+            off[2 * p] = (inc & 0xFFFFu) - s0;
             rowbase[2 * p + 1] = rowbase[2 * p] + (tot & 0xFFFFu);
-            off[2 * p + 1] = rowbase[2 * p + 1] + (inc >> 16) - s[2 * p + 1];
+            off[2 * p + 1] = (inc >> 16) - s1;
             rowbase[2 * p + 2] = rowbase[2 * p + 1] + (tot >> 16);
         }
         if (lane == 0) s_wave_tot[wave] = rowbase[kRows];
@@ -294,7 +355,6 @@ __global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__res
             tile_total += v;
         }
         if (wave == 0) {
-            const u64 epoch = ld_agent(&ctrl->epoch);
             const u64 prefix = resolve_prefix(status, tile, epoch, spin_limit, tile_total, [=](long long tl) {
                 return tile_width8(frame, head, end, tl);
             });
@@ -303,27 +363,32 @@ __global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__res
                 if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
             }
         }
-        uint8_t *wst8 = (uint8_t *)(stage + wave * kStageWords16);
-        uint32_t gof[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) gof[r] = off[r] - rowbase[(r / kGroup) * kGroup];
-        encode_group_any(cls, t, 0, gof, vm, wst8);
         __syncthreads();   // the tile prefix is known
+        uint32_t *wst = stage + wave * kStageWords16;
+        uint8_t *wst8 = (uint8_t *)wst;
         const u64 base = s_prefix + wave_off;
 #pragma unroll
-        for (int g = 0; g < kRows / kGroup; ++g) {
-            if (g > 0) encode_group_any(cls, t, g * kGroup, gof, vm, wst8);
+        for (int r = 0; r < kRows; ++r) {
+            const u64 b0 = base + rowbase[r];
+            const uint32_t s = (uint32_t)((uintptr_t)(out + b0) & 15u);
+            switch (cls) {
+                case kAscii16: narrow_row(t, r, s, wst, lane); break;
+                case kUpTo2B: encode_row<kUpTo2B>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                case kBmp: encode_row<kBmp>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                default: encode_row<kAnyUnit>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+            }
             wave_lds_sync();
-            const u64 b0 = base + rowbase[g * kGroup];
-            u64 nbytes = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
+            u64 nbytes = rowbase[r + 1] - rowbase[r];
             if (b0 >= out_cap) nbytes = 0;
             else if (b0 + nbytes > out_cap) nbytes = out_cap - b0;
-            write_out<1, kWave>(out + b0, nbytes, (const uint32_t *)wst8, lane);
+            write_out_aligned<1, kWave>(out + b0, nbytes, wst, lane);
             wave_lds_sync();
         }
     }
 
-    if (cls == kAnyUnit) {
+    // the first unpaired surrogate, unless an error before the wave is known
+    if (cls == kAnyUnit && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
+        u64 err = lane_first_error16(t, wbase, head, end, lane);
         err = wave_min_u64(err);
         if (lane == 0 && err != ~0ull) min_agent(&ctrl->err, err);
     }

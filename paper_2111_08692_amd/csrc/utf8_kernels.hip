@@ -39,58 +39,29 @@ enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kAny = 3 };
 // one slot per byte of the group plus one: a group can end with the leading
 // byte of a four-byte character (two slots) whose continuation bytes lie
 // beyond it.  Invalid input can announce up to two per byte; then only the
-// slots of the valid prefix (which fit) are kept.
+// slots of the valid prefix (which fit) are kept.  Decoded words are
+// written over the windows, shifted by up to seven words.
 constexpr uint32_t kStageSlots = kGroup * kRowBytes + 8;
-constexpr int kStageWords = (int)kStageSlots + 4;   // one dword per slot, per wave
-
-// Frame byte q with positions outside [head, end) read as zero.
-__device__ __forceinline__ uint32_t frame_byte(const uint8_t *frame, long long q, long long head, long long end) {
-    return (q >= head && q < end) ? (uint32_t)frame[q] : 0u;
-}
+constexpr int kStageWords = (int)kStageSlots + 8;   // one dword per slot, per wave
 
 __device__ __forceinline__ bool is_cont(uint32_t b) { return (b & 0xC0u) == 0x80u; }
 
-// Kind of the character announced at non-continuation byte q (0 if it is
-// valid), in the order rule 1, rule 2, then rules 4, 5, 6.
-__device__ uint32_t lead_kind(const uint8_t *frame, long long q, long long head, long long end) {
-    const uint32_t b0 = frame_byte(frame, q, head, end);
+// Kind of the character announced at non-continuation byte b0 followed by
+// b1, b2, b3 (0 if it is valid), in the order rule 1, rule 2, then rules
+// 4, 5, 6.  Bytes past the end of the input read as zero.
+__device__ __forceinline__ uint32_t lead_kind(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3) {
     if (b0 < 0x80u) return kOk;
     if (b0 >= 0xF8u) return kHeaderBits;
     const int len = b0 < 0xE0u ? 2 : (b0 < 0xF0u ? 3 : 4);
-    uint32_t cp = b0 & (0x7Fu >> len);
-    for (int k = 1; k < len; ++k) {
-        const uint32_t b = frame_byte(frame, q + k, head, end);
-        if (!is_cont(b)) return kTooShort;
-        cp = (cp << 6) | (b & 0x3Fu);
-    }
+    if (!is_cont(b1) || (len > 2 && !is_cont(b2)) || (len > 3 && !is_cont(b3))) return kTooShort;
+    uint32_t cp = ((b0 & (0x7Fu >> len)) << 6) | (b1 & 0x3Fu);
+    if (len > 2) cp = (cp << 6) | (b2 & 0x3Fu);
+    if (len > 3) cp = (cp << 6) | (b3 & 0x3Fu);
     const uint32_t lo = len == 2 ? 0x80u : (len == 3 ? 0x800u : 0x10000u);
     if (cp < lo) return kOverlong;
     if (cp > 0x10FFFFu) return kTooLarge;
     if (cp >= 0xD800u && cp <= 0xDFFFu) return kSurrogate;
     return kOk;
-}
-
-// Exact C over frame positions [qlo, qhi): min (position << 4 | kind).
-__device__ __noinline__ u64 exact_scan(const uint8_t *frame, long long head, long long end, long long qlo,
-                                       long long qhi) {
-    if (qlo < head) qlo = head;
-    if (qhi > end) qhi = end;
-    for (long long q = qlo; q < qhi; ++q) {
-        const uint32_t b0 = frame_byte(frame, q, head, end);
-        uint32_t kind = kOk;
-        if (is_cont(b0)) {
-            const uint32_t p1 = frame_byte(frame, q - 1, head, end);
-            const uint32_t p2 = frame_byte(frame, q - 2, head, end);
-            const uint32_t p3 = frame_byte(frame, q - 3, head, end);
-            const bool covered = p1 >= 0xC0u || (p2 >= 0xE0u && is_cont(p1)) ||
-                                 (p3 >= 0xF0u && is_cont(p2) && is_cont(p1));
-            if (!covered) kind = kTooLong;
-        } else {
-            kind = lead_kind(frame, q, head, end);
-        }
-        if (kind != kOk) return ((u64)(q - head) << 4) | kind;
-    }
-    return ~0ull;
 }
 
 // Bit 7 of every byte: byte >= C0, >= E0, >= F0; continuation.
@@ -278,166 +249,323 @@ __device__ __noinline__ u64 tile_width16(const uint8_t *frame, long long head, l
 // ------------------------------------------------------------------------
 // Step 1: leading bytes store their windows at their output slots.
 // ------------------------------------------------------------------------
+// Every byte position of the chunk stores its window, in position order,
+// at the slot of the next leading byte (its own slot if it is one); a
+// continuation byte's window is thus overwritten by the leading byte that
+// follows it in the same lane.  Only the first slot of the lane can keep a
+// stray window (from the previous lane's trailing continuation bytes); the
+// lane rewrites it at the end.  If the lane's first dword holds no leading
+// byte the input is invalid there and every slot of the lane lies past the
+// valid prefix, so nothing needs rewriting (waves at the ends of the input
+// look for the first leading byte anywhere in the chunk).
+//
 // The window of a four-byte character's low surrogate is stored with its
-// first byte xor 0x70, which maps F0..F4 into the continuation range 80..84
+// first byte xor 0x70, which maps F0..FF into the continuation range 80..8F
 // -- a value no leading byte's window starts with.
 template <uint32_t kClass>
-__device__ __forceinline__ void scatter_rows(const LaneBytes &t, int r0, const uint32_t (&gof)[kRows],
-                                             uint32_t *wst, long long wbase, long long head, long long end,
-                                             uint32_t lane) {
+__device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t gof, uint32_t *wst, long long wbase,
+                                            long long head, long long end, uint32_t lane) {
+    uint8_t *sb = (uint8_t *)wst;
+    constexpr uint32_t kLast = 4u * (kStageSlots - 2);   // invalid input may announce more slots
+    uint32_t o = 4u * gof;
+    const uint32_t nx_row = next_dword(t, r, lane);
+    uint32_t lead0 = 0;
 #pragma unroll
-    for (int r = r0; r < r0 + kGroup; ++r) {
-        uint32_t o = gof[r];
-        const uint32_t nx_row = next_dword(t, r, lane);
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t x = t.d[r][j];
+        const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
+        const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+        if (j == 0) lead0 = lead;
+        const uint32_t f0 = kClass == kAny ? ge_f0(x) & 0x80808080u : 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t x = t.d[r][j];
-            const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
-            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
-            const uint32_t f0 = kClass == kAny ? ge_f0(x) & 0x80808080u : 0u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((lead >> (8 * k + 7)) & 1u) {
-                    const uint32_t win = window4(x, nx, k);
-                    if (o < kStageSlots) wst[o] = win;
-                    if (kClass == kAny && ((f0 >> (8 * k + 7)) & 1u)) {
-                        if (o + 1 < kStageSlots) wst[o + 1] = win ^ 0x70u;
-                        o += 2;
-                    } else {
-                        o += 1;
-                    }
-                }
-            }
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t win = window4(x, nx, k);
+            const uint32_t a = kClass == kAny ? min(o, kLast) : o;
+            const uint32_t fb = kClass == kAny ? __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1) << 2 : 0u;
+            // the marked copy goes to the next slot for a four-byte leading
+            // byte, else to this slot, where the plain window replaces it
+            if (kClass == kAny) *(uint32_t *)(sb + a + fb) = win ^ 0x70u;
+            *(uint32_t *)(sb + a) = win;
+            o += (__builtin_amdgcn_ubfe(lead, 8 * k + 7, 1) << 2) + fb;
         }
+    }
+    // rewrite the first slot
+    uint32_t win = 0;
+    bool has = false;
+    if (!t.edge) {
+        has = lead0 != 0;
+        const uint32_t p = (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3;   // first leading byte
+        win = __builtin_amdgcn_alignbyte(t.d[r][1], t.d[r][0], p);
+    } else {
+        uint32_t p = 16;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+            if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
+        }
+        has = p < 16;
+        const uint32_t j = p >> 2;
+        const uint32_t lo = j == 0 ? t.d[r][0] : (j == 1 ? t.d[r][1] : (j == 2 ? t.d[r][2] : t.d[r][3]));
+        const uint32_t hi = j == 0 ? t.d[r][1] : (j == 1 ? t.d[r][2] : (j == 2 ? t.d[r][3] : nx_row));
+        win = __builtin_amdgcn_alignbyte(hi, lo, p & 3u);
+    }
+    if (has) {
+        const uint32_t a = kClass == kAny ? min(4u * gof, kLast) : 4u * gof;
+        *(uint32_t *)(sb + a) = win;
     }
 }
 
 // ------------------------------------------------------------------------
 // Step 2: decode windows into UTF-16 words.
 // ------------------------------------------------------------------------
-// Word of the window `w` (low byte = leading byte).  `bad` is set when a
-// value rule (or rule 1) fails for the character; structure (continuation
-// bytes) is checked by the detector.
+// Word of the window `w` (low byte = leading byte), without branches.
+// `bad` is set when a value rule (or rule 1) fails for the character;
+// structure (continuation bytes) is checked by the detector.
+// Pins two values in registers where they are computed, so that later
+// selects between them stay selects.
+__device__ __forceinline__ void opaque(uint32_t &a, uint32_t &b) { asm volatile("" : "+v"(a), "+v"(b)); }
+
 template <uint32_t kClass>
-__device__ __forceinline__ uint32_t decode_window(uint32_t w, bool &bad) {
+__device__ __forceinline__ uint32_t decode_word(uint32_t w, bool &bad) {
     if (kClass == kUpTo2) {
         const uint32_t b0 = w & 0xFFu;
-        const bool l2 = b0 >= 0xC0u;
-        const uint32_t u = l2 ? (((b0 & 0x1Fu) << 6) | ((w >> 8) & 0x3Fu)) : b0;
-        bad |= l2 && u < 0x80u;
-        return u;
+        uint32_t c2 = ((w & 0x1Fu) << 6) | ((w >> 8) & 0x3Fu);
+        opaque(c2, c2);
+        bad |= (w & 0xFEu) == 0xC0u;                          // C0, C1: overlong
+        return b0 >= 0xC0u ? c2 : b0;
     }
     bool low = false;
     if (kClass == kAny) {
-        low = (w & 0xC0u) == 0x80u;
-        if (low) w ^= 0x70u;
+        low = (w & 0xC0u) == 0x80u;                            // marked low-surrogate copy
+        w ^= low ? 0x70u : 0u;
     }
     const uint32_t b0 = w & 0xFFu;
-    const uint32_t len = 1u + (b0 >= 0xC0u) + (b0 >= 0xE0u) + (kClass == kAny ? (uint32_t)(b0 >= 0xF0u) : 0u);
-    const uint32_t c18 = (((w >> 8) & 0x3Fu) << 12) | (((w >> 16) & 0x3Fu) << 6) | ((w >> 24) & 0x3Fu);
-    const uint32_t lp = b0 & (0x7Fu >> (len == 1u ? 0u : len));
-    const uint32_t cp = ((lp << 18) | c18) >> (6u * (4u - len));
-    const uint32_t lo = len == 1u ? 0u : (len == 2u ? 0x80u : (len == 3u ? 0x800u : 0x10000u));
-    bad |= (cp < lo) | ((cp & 0xFFFFF800u) == 0xD800u);
-    if (kClass == kUpTo3) return cp;
-    bad |= (b0 >= 0xF8u) | (cp > 0x10FFFFu);
-    if (len == 4u) return low ? (0xDC00u | (cp & 0x3FFu)) : (0xD7C0u + (cp >> 10));
-    return cp;
+    const uint32_t x1 = (w >> 8) & 0x3Fu;
+    const uint32_t x2 = (w >> 16) & 0x3Fu;
+    uint32_t c2 = ((w & 0x1Fu) << 6) | x1;
+    uint32_t c3 = ((w & 0x0Fu) << 12) | (x1 << 6) | x2;
+    opaque(c2, c3);   // computed for every word: selects, not branches
+    const bool l3 = b0 >= 0xE0u;
+    // three-byte value below U+0800 (top five bits 0) or a surrogate (11011)
+    const bool b3 = (0x08000001u >> (c3 >> 11)) & 1u;
+    uint32_t u = l3 ? c3 : (b0 >= 0xC0u ? c2 : b0);
+    if (kClass == kUpTo3) {
+        bad |= ((w & 0xFEu) == 0xC0u) | (l3 & b3);
+        return u;
+    }
+    // four bytes: rule 1 (F8..FF) lands above U+10FFFF through the fourth
+    // payload bit kept here
+    const bool l4 = b0 >= 0xF0u;
+    const uint32_t c4 = ((w & 0x0Fu) << 18) | (x1 << 12) | (x2 << 6) | ((w >> 24) & 0x3Fu);
+    bad |= ((w & 0xFEu) == 0xC0u) | (l3 & !l4 & b3) | (l4 & (c4 - 0x10000u > 0xFFFFFu));
+    uint32_t hi = 0xD7C0u + (c4 >> 10), lo = 0xDC00u | (c4 & 0x3FFu);
+    opaque(hi, lo);
+    const uint32_t sur = low ? lo : hi;
+    return l4 ? sur : u;
 }
 
-// Decode the group's slots and store words [u0, u0 + nslots) of the output
-// (only those below out_cap are stored; every slot is decoded so the value
-// rules are checked for every character).
+// Decode the group's slots [0, nslots) in place: slot s's word goes to
+// halfword h + s of the stage (lane-strided, so consecutive lanes touch
+// consecutive LDS banks).  A pass reads its windows before it writes, and
+// its writes land below the windows of later passes.
 template <uint32_t kClass>
-__device__ __forceinline__ bool decode_store(uint16_t *out, u64 out_cap, u64 u0, uint32_t nslots,
-                                             const uint32_t *wst, uint32_t lane) {
+__device__ __forceinline__ bool decode_slots(uint32_t *wst, uint32_t nslots, uint32_t h, uint32_t lane) {
+    constexpr int kU = 2;   // a pass covers 128 slots: little waste on the last one
+    uint16_t *w16 = (uint16_t *)wst;
     bool bad = false;
-    if (nslots > kStageSlots) nslots = kStageSlots;
-    if (nslots == 0) return false;
-    const uintptr_t g0 = (uintptr_t)(out + u0);
-    const uintptr_t g1 = g0 + 2 * (uintptr_t)nslots;
-    const uintptr_t gcap = out_cap > u0 ? g0 + 2 * (uintptr_t)(out_cap - u0) : g0;
-    const uintptr_t c0 = g0 & ~(uintptr_t)15;
-    const uintptr_t cend = (g1 + 15) & ~(uintptr_t)15;
-    for (uintptr_t c = c0 + 16 * (uintptr_t)lane; c < cend; c += 16 * kWave) {
-        if (c >= g0 && c + 16 <= g1) {
-            const uint32_t *w = wst + ((c - g0) >> 1);
-            uint32_t u[8];
+    for (uint32_t s0 = 0; s0 < nslots; s0 += kU * kWave) {
+        uint32_t w[kU];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) u[i] = decode_window<kClass>(w[i], bad);
-            if (c + 16 <= gcap) {
-                const u32x4 v = {u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16), u[6] | (u[7] << 16)};
-                __builtin_nontemporal_store(v, (u32x4 *)c);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (c + 2 * i < gcap) *(uint16_t *)(c + 2 * i) = (uint16_t)u[i];
-            }
-        } else {
-            for (uintptr_t a = c; a < c + 16; a += 2) {
-                if (a >= g0 && a < g1) {
-                    const uint32_t v = decode_window<kClass>(wst[(a - g0) >> 1], bad);
-                    if (a < gcap) *(uint16_t *)a = (uint16_t)v;
-                }
-            }
+        for (int i = 0; i < kU; ++i) {
+            const uint32_t s = s0 + i * kWave + lane;
+            w[i] = s < nslots ? wst[s] : 0x20u;
         }
+        uint32_t u[kU];
+#pragma unroll
+        for (int i = 0; i < kU; ++i) u[i] = decode_word<kClass>(w[i], bad);
+#pragma unroll
+        for (int i = 0; i < kU; ++i) w16[h + s0 + i * kWave + lane] = (uint16_t)u[i];
     }
     return bad;
 }
 
-// ASCII groups: widen bytes to words in the stage, then copy them out.
-__device__ __forceinline__ void widen_rows(const LaneBytes &t, int r0, const uint32_t (&gof)[kRows],
-                                           uint32_t *wst) {
-    uint16_t *st16 = (uint16_t *)wst;
-#pragma unroll
-    for (int r = r0; r < r0 + kGroup; ++r) {
-        uint32_t w[8];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            w[2 * k] = __builtin_amdgcn_perm(0u, t.d[r][k], 0x0c010c00u);
-            w[2 * k + 1] = __builtin_amdgcn_perm(0u, t.d[r][k], 0x0c030c02u);
-        }
-        u32x4 *dst = (u32x4 *)(st16 + gof[r]);   // a multiple of 16 words in an all-ASCII wave
-        dst[0] = u32x4{w[0], w[1], w[2], w[3]};
-        dst[1] = u32x4{w[4], w[5], w[6], w[7]};
+// ------------------------------------------------------------------------
+// All-ASCII waves: every byte is one word, written straight from registers.
+// ------------------------------------------------------------------------
+// Bytes q..q+7 (0 < q < 8, wave-uniform) of the 16 bytes a0..a3.
+__device__ __forceinline__ void bytes8(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t q,
+                                       uint32_t &lo, uint32_t &hi) {
+    const uint32_t sh = q & 3u;
+    if (q < 4) {
+        lo = __builtin_amdgcn_alignbyte(a1, a0, sh);
+        hi = __builtin_amdgcn_alignbyte(a2, a1, sh);
+    } else {
+        lo = __builtin_amdgcn_alignbyte(a2, a1, sh);
+        hi = __builtin_amdgcn_alignbyte(a3, a2, sh);
     }
 }
 
-// The wave's conversion after the tile prefix is known (group 0 has been
-// staged already).  Returns whether a value rule failed.
+__device__ __forceinline__ u32x4 widen8(uint32_t lo, uint32_t hi) {
+    return u32x4{__builtin_amdgcn_perm(0u, lo, 0x0c010c00u), __builtin_amdgcn_perm(0u, lo, 0x0c030c02u),
+                 __builtin_amdgcn_perm(0u, hi, 0x0c010c00u), __builtin_amdgcn_perm(0u, hi, 0x0c030c02u)};
+}
+
+// The wave's words [u0, u0 + kWaveBytes) of `out` (all inside the output
+// capacity).  Lane L of row r holds words 1024 r + 16 L .. +16.  With the
+// first word at byte s of a 16-byte block, lane L stores the block that
+// starts 16 - s bytes into its 32 output bytes and the block that starts
+// 32 - s bytes in (finished with the first bytes of the next lane); the
+// part blocks at the two ends of the wave take 2-byte stores.  The stores
+// are ordinary (cached) ones: each instruction covers every other 16-byte
+// block, which the L2 merges into whole lines before they reach HBM.
+__device__ __forceinline__ void widen_store_wave(const LaneBytes &t, uint16_t *out, u64 u0, uint32_t lane) {
+    uint8_t *g0 = (uint8_t *)(out + u0);
+    const uint32_t s = (uint32_t)((uintptr_t)g0 & 15u);   // even
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        uint8_t *g = g0 + 2 * kRowBytes * r + 32 * lane;
+        const uint32_t *d = t.d[r];
+        if (s == 0) {
+            *(u32x4 *)g = widen8(d[0], d[1]);
+            *(u32x4 *)(g + 16) = widen8(d[2], d[3]);
+            continue;
+        }
+        const uint32_t q = 8u - s / 2u;   // first input byte of the block
+        uint32_t n0 = __shfl_down(d[0], 1), n1 = __shfl_down(d[1], 1);
+        if (r + 1 < kRows) {
+            const uint32_t m0 = readlane(t.d[r + 1][0], 0), m1 = readlane(t.d[r + 1][1], 0);
+            if (lane == kWave - 1) {
+                n0 = m0;
+                n1 = m1;
+            }
+        }
+        uint32_t lo, hi;
+        bytes8(d[0], d[1], d[2], d[3], q, lo, hi);
+        *(u32x4 *)(g + 16 - s) = widen8(lo, hi);
+        if (r + 1 < kRows || lane + 1 < kWave) {
+            bytes8(d[2], d[3], n0, n1, q, lo, hi);
+            *(u32x4 *)(g + 32 - s) = widen8(lo, hi);
+        }
+        if (r == 0 && lane == 0) {   // head: words 0 .. q-1
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if ((uint32_t)k < q) ((uint16_t *)g)[k] = (uint16_t)((d[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+        }
+        if (r == kRows - 1 && lane == kWave - 1) {   // tail: words 16 - s/2 .. 15
+#pragma unroll
+            for (int k = 9; k < 16; ++k)
+                if ((uint32_t)k >= 16u - s / 2u)
+                    ((uint16_t *)g)[k] = (uint16_t)((d[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+        }
+    }
+}
+
+// The wave's conversion after the tile prefix is known.  `staged0`: group
+// 0 has been staged already.  Returns whether a value rule failed.
 template <uint32_t kClass>
 __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
                                              const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
                                              u64 out_cap, uint32_t *wst, long long wbase, long long head,
-                                             long long end, uint32_t lane) {
+                                             long long end, uint32_t lane, bool staged0) {
     bool bad = false;
 #pragma unroll
     for (int g = 0; g < kRows / kGroup; ++g) {
-        if (g > 0) {
-            if (kClass == kAscii) widen_rows(t, g * kGroup, gof, wst);
-            else scatter_rows<kClass>(t, g * kGroup, gof, wst, wbase, head, end, lane);
-        }
+        if (g > 0 || !staged0)
+#pragma unroll
+            for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
+                scatter_row<kClass>(t, r, gof[r], wst, wbase, head, end, lane);
         wave_lds_sync();
         const u64 u0 = base + rowbase[g * kGroup];
-        const uint32_t nslots = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
-        if (kClass == kAscii) {
-            u64 nunits = nslots;
-            if (u0 >= out_cap) nunits = 0;
-            else if (u0 + nunits > out_cap) nunits = out_cap - u0;
-            write_out<2, kWave>((uint8_t *)(out + u0), 2 * nunits, wst, lane);
-        } else {
-            bad |= decode_store<kClass>(out, out_cap, u0, nslots, wst, lane);
-        }
+        uint32_t nslots = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
+        if (nslots > kStageSlots) nslots = kStageSlots;   // only past an error
+        const uint32_t h = (uint32_t)(((uintptr_t)(out + u0) >> 1) & 7u);
+        bad |= decode_slots<kClass>(wst, nslots, h, lane);
+        wave_lds_sync();
+        u64 nunits = nslots;
+        if (u0 >= out_cap) nunits = 0;
+        else if (u0 + nunits > out_cap) nunits = out_cap - u0;
+        write_out_aligned<2, kWave>((uint8_t *)(out + u0), 2 * nunits, wst, lane);
         wave_lds_sync();
     }
     return bad;
 }
 
-// Validation only: decode every leading byte's window in registers.
+// ------------------------------------------------------------------------
+// Validation only: value rules on every leading byte, from its byte and
+// the next (SWAR over the dword x, with y = the bytes one position later).
+// ------------------------------------------------------------------------
+// Bit 7 of every zero byte of t.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t t) {
+    return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+}
+
 template <uint32_t kClass>
-__device__ __forceinline__ bool check_values(const LaneBytes &t, long long wbase, long long head, long long end,
-                                             uint32_t lane) {
-    bool bad = false;
+__device__ __forceinline__ uint32_t value_bits(uint32_t x, uint32_t y) {
+    uint32_t bad = zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);            // C0, C1
+    if (kClass == kUpTo2) return bad;
+    const uint32_t y5 = y << 2;                                              // bit 5 of the next byte
+    bad |= zero_bytes(x ^ 0xE0E0E0E0u) & ~y5;                                // E0 80..9F: overlong
+    bad |= zero_bytes(x ^ 0xEDEDEDEDu) & y5;                                 // ED A0..BF: surrogate
+    if (kClass == kUpTo3) return bad;
+    const uint32_t y54 = (y << 2) | (y << 3);                                // bit 5 or 4 of the next byte
+    bad |= zero_bytes(x ^ 0xF0F0F0F0u) & ~y54;                               // F0 80..8F: overlong
+    bad |= zero_bytes(x ^ 0xF4F4F4F4u) & y54;                                // F4 90..BF: too large
+    bad |= ((x & 0x7F7F7F7Fu) + 0x0B0B0B0Bu) & x;                            // F5..FF
+    return bad & 0x80808080u;
+}
+
+// ------------------------------------------------------------------------
+// Exact first error of a lane's chunk (flagged waves only)
+// ------------------------------------------------------------------------
+// With the bytes in registers -- v = {dword before the chunk, the chunk's
+// four dwords, dword after it} -- the smallest position of C is the first
+// byte flagged by any of: a continuation byte that no byte in reach
+// announces (cont and not must), a leading byte whose announced
+// continuation bytes are not all there, a leading byte whose value rules
+// fail (from it and the next byte).  Each flag implies C at its position,
+// and the first position of C carries one of them, so the first flag is
+// the first error.  With `halo`, the leading bytes among the three
+// positions before the chunk are examined too (a continuation byte there
+// belongs to the previous wave, whose detector fires at it when it is the
+// first error).  Returns min (position << 4 | kind) or ~0.  Kept small: it
+// runs in few waves, usually with its code not in the instruction cache.
+__device__ __noinline__ u64 exact_chunk(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3, uint32_t v4,
+                                        uint32_t v5, long long q0, long long head, bool halo) {
+    const uint32_t v[6] = {v0, v1, v2, v3, v4, v5};
+    uint32_t first = 32;   // byte index into v (chunk position + 4)
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {   // backwards: the smallest index is kept
+        const uint32_t x = v[i], xn = v[i + 1], xp = i > 0 ? v[i - 1] : 0u;
+        const uint32_t c0 = ge_c0(x), e0 = ge_e0(x), f0 = ge_f0(x);
+        const uint32_t shortb = (c0 & ~cont_bits(__builtin_amdgcn_alignbyte(xn, x, 1))) |
+                                (e0 & ~cont_bits(__builtin_amdgcn_alignbyte(xn, x, 2))) |
+                                (f0 & ~cont_bits(__builtin_amdgcn_alignbyte(xn, x, 3)));
+        const uint32_t lead_bad = (shortb | value_bits<kAny>(x, __builtin_amdgcn_alignbyte(xn, x, 1))) & 0x80808080u;
+        uint32_t bad;
+        if (i == 0) {
+            bad = halo ? lead_bad & 0x80808000u : 0u;
+        } else {
+            const uint32_t must = __builtin_amdgcn_alignbyte(c0, ge_c0(xp), 3) |
+                                  __builtin_amdgcn_alignbyte(e0, ge_e0(xp), 2) |
+                                  __builtin_amdgcn_alignbyte(f0, ge_f0(xp), 1);
+            bad = lead_bad | (cont_bits(x) & ~must & 0x80808080u);
+        }
+        if (bad) first = 4 * i + ((uint32_t)__builtin_ctz(bad) >> 3);
+    }
+    if (first == 32) return ~0ull;
+    const uint32_t wi = first >> 2;
+    const uint32_t lo = wi == 0 ? v0 : (wi == 1 ? v1 : (wi == 2 ? v2 : (wi == 3 ? v3 : v4)));
+    const uint32_t hi = wi == 0 ? v1 : (wi == 1 ? v2 : (wi == 2 ? v3 : (wi == 3 ? v4 : v5)));
+    const uint32_t w = __builtin_amdgcn_alignbyte(hi, lo, first & 3u);
+    const uint32_t b0 = w & 0xFFu;
+    const uint32_t kind = is_cont(b0) ? (uint32_t)kTooLong
+                                      : lead_kind(b0, (w >> 8) & 0xFFu, (w >> 16) & 0xFFu, w >> 24);
+    return ((u64)(q0 + (long long)first - 4 - head) << 4) | kind;
+}
+
+template <uint32_t kClass>
+__device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) {
+    uint32_t bad = 0;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const uint32_t nx_row = next_dword(t, r, lane);
@@ -445,13 +573,10 @@ __device__ __forceinline__ bool check_values(const LaneBytes &t, long long wbase
         for (int j = 0; j < 4; ++j) {
             const uint32_t x = t.d[r][j];
             const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
-            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if ((lead >> (8 * k + 7)) & 1u) (void)decode_window<kClass>(window4(x, nx, k), bad);
+            bad |= value_bits<kClass>(x, __builtin_amdgcn_alignbyte(nx, x, 1));
         }
     }
-    return bad;
+    return bad != 0;
 }
 
 // ------------------------------------------------------------------------
@@ -520,44 +645,54 @@ __global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__rest
             }
             uint32_t *wst = stage + wave * kStageWords;
             switch (cls) {   // the first group needs no prefix
-                case kAscii: widen_rows(t, 0, gof, wst); break;
-                case kUpTo2: scatter_rows<kUpTo2>(t, 0, gof, wst, wbase, head, end, lane); break;
-                case kUpTo3: scatter_rows<kUpTo3>(t, 0, gof, wst, wbase, head, end, lane); break;
-                default: scatter_rows<kAny>(t, 0, gof, wst, wbase, head, end, lane); break;
+                case kAscii: break;
+                case kUpTo2: scatter_row<kUpTo2>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                case kUpTo3: scatter_row<kUpTo3>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                default: scatter_row<kAny>(t, 0, gof[0], wst, wbase, head, end, lane); break;
             }
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
             switch (cls) {
                 case kAscii:
-                    convert_wave<kAscii>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    if (base + kWaveBytes <= out_cap)
+                        widen_store_wave(t, out, base, lane);
+                    else
+                        convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                                             false);
                     break;
                 case kUpTo2:
-                    flag |= convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    flag |= convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                                                 true);
                     break;
                 case kUpTo3:
-                    flag |= convert_wave<kUpTo3>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    flag |= convert_wave<kUpTo3>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                                                 true);
                     break;
                 default:
-                    flag |= convert_wave<kAny>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane);
+                    flag |= convert_wave<kAny>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                                               true);
                     break;
             }
         } else {
             switch (cls) {
                 case kAscii: break;
-                case kUpTo2: flag = flag || check_values<kUpTo2>(t, wbase, head, end, lane); break;
-                case kUpTo3: flag = flag || check_values<kUpTo3>(t, wbase, head, end, lane); break;
-                default: flag = flag || check_values<kAny>(t, wbase, head, end, lane); break;
+                case kUpTo2: flag = flag || check_values<kUpTo2>(t, lane); break;
+                case kUpTo3: flag = flag || check_values<kUpTo3>(t, lane); break;
+                default: flag = flag || check_values<kAny>(t, lane); break;
             }
         }
 
-        if (__ballot(flag)) {
-            // exact first error over this lane's positions (and, for the first
-            // lane, the three positions before the wave)
+        // exact first error over this lane's positions (and, for the first
+        // lane, the leading bytes among the three positions before the wave),
+        // unless an error before the wave is already known
+        if (__ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - 3 - head) {
             u64 err = ~0ull;
+#pragma unroll
             for (int r = 0; r < kRows; ++r) {
                 const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
-                const long long lo = (r == 0 && lane == 0) ? q0 - 3 : q0;
-                const u64 e = exact_scan(frame, head, end, lo, q0 + 16);
+                const uint32_t p = prev_dword(t, r, lane), nx = next_dword(t, r, lane);
+                const u64 e = exact_chunk(p, t.d[r][0], t.d[r][1], t.d[r][2], t.d[r][3], nx, q0, head,
+                                          r == 0 && lane == 0);
                 if (e < err) err = e;
             }
             err = wave_min_u64(err);

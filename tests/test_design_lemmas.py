@@ -20,9 +20,12 @@
    >= 0xF0 it drops the F0 term of must(), with no byte >= 0xE0 also the E0
    term, and with no byte >= 0x80 it raises nothing.  It flags when a
    mismatch occurs at one of its positions or a value rule fails at one of
-   its leading bytes, and a flagged wave evaluates C exactly over
-   [a-3, z).  Splitting a buffer into waves at any point, the smallest C
-   found this way is the greedy first error.
+   its leading bytes, and a flagged wave evaluates C exactly over its own
+   positions [a, z) and over the non-continuation positions of [a-3, a)
+   (a continuation byte there is judged by the wave that owns it, whose
+   detector fires at that very byte when it is the first error).
+   Splitting a buffer into waves at any point, the smallest C found this
+   way is the greedy first error.
 """
 import itertools
 
@@ -163,7 +166,8 @@ def wave_found(b, a, z):
     flag = flag or any(range_flag(b, i) for i in range(max(a, 0), min(z, n)))
     if not flag:
         return []
-    return [i for i in range(max(a - 3, 0), min(z, n)) if C(b, i)]
+    halo = [i for i in range(max(a - 3, 0), min(a, n)) if not is_cont(b[i]) and C(b, i)]
+    return halo + [i for i in range(max(a, 0), min(z, n)) if C(b, i)]
 
 
 def check_split(b):
@@ -191,3 +195,49 @@ def test_wave_control_random_long():
     for _ in range(6000):
         n = int(rng.integers(5, 14))
         check_split(alpha[rng.integers(0, alpha.size, size=n)].tolist())
+
+
+# 4. Exact first error from three byte-local flags.  A flagged wave finds
+#    its first error as the first position carrying one of: a continuation
+#    byte with must() false, a leading byte whose announced continuation
+#    bytes are not all continuations, a leading byte whose (lead, next byte)
+#    pair breaks a value rule (C0/C1; E0 80..9F; ED A0..BF; F0 80..8F;
+#    F4 90..BF; F5..FF).  Every flag implies C at its position and the first
+#    position of C carries a flag, so the first flag is the first error.
+
+def flags_at(b, i):
+    x = byte_at(b, i)
+    nxt = byte_at(b, i + 1)
+    if is_cont(x):
+        return not must(b, i)
+    if x < 0xC0:
+        return False
+    L = announced(x)
+    if any(not is_cont(byte_at(b, i + k)) for k in range(1, L)):
+        return True
+    return (x in (0xC0, 0xC1) or (x == 0xE0 and nxt < 0xA0) or (x == 0xED and nxt >= 0xA0)
+            or (x == 0xF0 and nxt < 0x90) or (x == 0xF4 and nxt >= 0x90) or x >= 0xF5)
+
+
+def check_first_flag(b):
+    st, e = O.validate_utf8(np.array(b, dtype=np.uint8))
+    fl = [i for i in range(len(b)) if flags_at(b, i)]
+    if st == 0:
+        assert not fl, bytes(b).hex()
+    else:
+        assert fl and fl[0] == e, (bytes(b).hex(), fl, e)
+        assert all(C(b, i) for i in fl), bytes(b).hex()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_first_flag_exhaustive(n):
+    for b in itertools.product(ALPHA, repeat=n):
+        check_first_flag(list(b))
+
+
+def test_first_flag_random_long():
+    rng = np.random.default_rng(9)
+    alpha = np.array(ALPHA + [0x20, 0x7F, 0xBE, 0xE4, 0xB8, 0xF1, 0xF3], dtype=np.uint8)
+    for _ in range(30000):
+        n = int(rng.integers(5, 14))
+        check_first_flag(alpha[rng.integers(0, alpha.size, size=n)].tolist())

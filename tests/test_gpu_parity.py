@@ -17,7 +17,6 @@ from workloads.mixes import UTF8_BAD_PATTERNS
 pytestmark = pytest.mark.gpu
 
 MIXES = ("mix1m",) + SCRIPT_MIXES
-TILE = 16384
 
 
 @pytest.fixture(scope="module")
@@ -98,6 +97,7 @@ def test_every_small_size_utf16(G, orc):
 
 @pytest.mark.parametrize("mix", MIXES)
 def test_multi_tile_ragged_utf8(G, orc, mix):
+    TILE = G.tile_bytes()   # input bytes per workgroup of the kernels
     for size in (TILE - 1, TILE, TILE + 1, 3 * TILE + 7, 100_003, 5 * TILE - 2):
         b = make_buffer(mix, size, seed=size)
         check_utf8(G, orc, b.data, label=f"{mix} {size}")
@@ -108,6 +108,7 @@ def test_multi_tile_ragged_utf8(G, orc, mix):
 
 @pytest.mark.parametrize("mix", MIXES)
 def test_multi_tile_ragged_utf16(G, orc, mix):
+    TILE = G.tile_bytes()   # input bytes per workgroup of the kernels
     for size in (TILE - 2, TILE, TILE + 2, 3 * TILE + 6, 100_002, 5 * TILE - 2):
         b = make_buffer(mix, size, seed=size, encoding="utf-16-le")
         check_utf16(G, orc, b.data, label=f"{mix} {size}")
@@ -152,6 +153,7 @@ def _utf8_patterns():
 
 @pytest.mark.parametrize("filler", ["ascii", "cjk", "emoji"])
 def test_boundary_straddle_utf8(G, orc, filler):
+    TILE = G.tile_bytes()   # input bytes per workgroup of the kernels
     pats = _utf8_patterns()
     for bnd in (16, 1024, 4096, TILE, 2 * TILE):
         for delta in range(-4, 5):
@@ -166,6 +168,7 @@ def test_boundary_straddle_utf8(G, orc, filler):
 
 @pytest.mark.parametrize("filler", ["ascii", "cjk", "emoji"])
 def test_boundary_straddle_utf16(G, orc, filler):
+    TILE = G.tile_bytes()   # input bytes per workgroup of the kernels
     pats = [np.frombuffer(c.encode("utf-16-le"), dtype="<u2") for c in VALID_CHARS]
     pats += [np.array(x, dtype=np.uint16) for x in ([0xD800], [0xDBFF], [0xDC00], [0xDFFF], [0xDC00, 0xD800],
                                                     [0xD83D, 0xD83D, 0xDE00])]
@@ -198,6 +201,7 @@ def test_random_edge_bytes(G, orc):
 
 
 def test_random_bytes_long(G, orc):
+    TILE = G.tile_bytes()   # input bytes per workgroup of the kernels
     """Uniform random bytes: width up to 2 words per byte (stage clamp)."""
     rng = np.random.default_rng(10)
     for n in (5000, TILE, 3 * TILE + 5):
