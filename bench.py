@@ -129,14 +129,45 @@ def cpu_baseline(bufs, sample_bytes: int):
 # main
 # ---------------------------------------------------------------------------
 
+def one_mib_latency(G, small, dev, stream, res, aux):
+    """Latency of one synchronous 1 MiB call and the kernel time of one
+    asynchronous call (the single-buffer 1 MiB case)."""
+    import torch
+    ds = torch.from_numpy(small.data).to(dev)
+    o16 = torch.empty(small.data.size, dtype=torch.int16, device=dev)
+    for _ in range(20):
+        G.convert_utf8_to_utf16le(ds, out=o16)
+    lat = []
+    for _ in range(200):
+        t = time.perf_counter()
+        st, cnt, _ = G.convert_utf8_to_utf16le(ds, out=o16)
+        lat.append(time.perf_counter() - t)
+    assert st == 0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for s_, e_ in ev:
+        s_.record(stream)
+        G.convert_utf8_to_utf16le_async(ds, o16, res[0])
+        e_.record(stream)
+    torch.cuda.synchronize()
+    kt = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
+    aux["mix1m_8to16_sync_call_us_p50"] = round(statistics.median(lat) * 1e6, 1)
+    aux["mix1m_8to16_kernel_us"] = round(kt * 1e6, 1)
+    aux["mix1m_8to16_kernel_input_GBps"] = round(small.data.size / kt / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size-mib", type=int, default=1024, help="bytes per buffer (MiB); the workload is 1024")
-    ap.add_argument("--cpu-sample-mib", type=int, default=256)
+    ap.add_argument("--cpu-sample-mib", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-aux", action="store_true",
+                    help="skip the validate-only / length-only / 1 MiB latency figures (for profiled runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer three times (a plain copy kernel of known size, "
+                         "the reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -144,6 +175,18 @@ def main():
                                    "(the transcoder is a single-GPU path, see DESIGN.md for how it would shard)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.full((n,), 65, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
+        return
 
     size = args.size_mib << 20
     bufs, small = generate(size)
@@ -253,8 +296,8 @@ def main():
                 "avg_launch_ms": round(kern_time[dom] / launches * 1e3, 4)}
 
     # auxiliary kernels: validate-only and length-only on the valid buffers
-    aux = {}
-    for name, fn in (("validate", None), ("length", None)):
+    aux = None if args.no_aux else {}
+    for name, fn in (() if args.no_aux else (("validate", None), ("length", None))):
         tt, nb = 0.0, 0
         for i, ((mix, enc, kind, b), d) in enumerate(zip(bufs, dbufs)):
             if kind != "valid":
@@ -275,26 +318,8 @@ def main():
         aux[f"{name}_only_roofline_frac"] = round(nb / tt / 1e9 / HBM_PEAK_GBS, 3)
 
     # the 1 MiB single buffer: latency of one synchronous call
-    ds = torch.from_numpy(small.data).to(dev)
-    o16 = torch.empty(small.data.size, dtype=torch.int16, device=dev)
-    for _ in range(20):
-        G.convert_utf8_to_utf16le(ds, out=o16)
-    lat = []
-    for _ in range(200):
-        t = time.perf_counter()
-        st, cnt, _ = G.convert_utf8_to_utf16le(ds, out=o16)
-        lat.append(time.perf_counter() - t)
-    assert st == 0
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
-    for s_, e_ in ev:
-        s_.record(stream)
-        G.convert_utf8_to_utf16le_async(ds, o16, res[0])
-        e_.record(stream)
-    torch.cuda.synchronize()
-    kt = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
-    aux["mix1m_8to16_sync_call_us_p50"] = round(statistics.median(lat) * 1e6, 1)
-    aux["mix1m_8to16_kernel_us"] = round(kt * 1e6, 1)
-    aux["mix1m_8to16_kernel_input_GBps"] = round(small.data.size / kt / 1e9, 1)
+    if not args.no_aux:
+        one_mib_latency(G, small, dev, stream, res, aux)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(bufs, args.cpu_sample_mib << 20)
 
