@@ -241,3 +241,87 @@ def test_first_flag_random_long():
     for _ in range(30000):
         n = int(rng.integers(5, 14))
         check_first_flag(alpha[rng.integers(0, alpha.size, size=n)].tolist())
+
+
+# 5. Slot write order of the UTF-8 -> UTF-16 scatter.  Per row, lane L
+#    holds bytes 16L..16L+15; its first slot is the exclusive prefix of
+#    the lanes' slot counts (one per non-continuation byte, one more per
+#    byte >= F0 when the wave has one).  Instruction k (k = 0..15) has every
+#    lane store the window of its byte k at the slot of its next leading
+#    byte (and, with bytes >= F0 about, a marked copy first: at the next
+#    slot for a byte >= F0, else at the same slot).  Afterwards each lane
+#    rewrites its first slot with its first leading byte's window (waves in
+#    the middle of the input only look in the chunk's first dword).  The
+#    slots of every character before the first error must hold that
+#    character's window, whatever order the lanes of one instruction take.
+
+def scatter_model(row, lo, hi, kany, lane_order, edge):
+    b = [row[i] if lo <= i < hi else 0 for i in range(len(row))]
+    lead = [lo <= i < hi and not is_cont(b[i]) for i in range(1024)]
+    f0 = [kany and b[i] >= 0xF0 for i in range(1024)]
+    width = [sum(int(lead[16 * L + k]) + int(f0[16 * L + k]) for k in range(16)) for L in range(64)]
+    base = [sum(width[:L]) for L in range(64)]
+    last = 1032 - 2
+    o = list(base)
+    stage = {}
+    win = lambda i: b[i] | b[i + 1] << 8 | b[i + 2] << 16 | b[i + 3] << 24
+    for k in range(16):
+        marked, plain = [], []
+        for L in range(64):
+            i = 16 * L + k
+            a = min(o[L], last) if kany else o[L]
+            if kany:
+                marked.append((L, a + int(f0[i]), win(i) ^ 0x70))
+            plain.append((L, a, win(i)))
+            o[L] += int(lead[i]) + int(f0[i])
+        for group in (marked, plain):
+            for L, a, v in sorted(group, reverse=(lane_order == "high")):
+                assert a < 1032
+                stage[a] = v
+    for L in range(64):
+        first = [k for k in range(16) if lead[16 * L + k]]
+        if not first or (not edge and first[0] > 3):
+            continue
+        stage[min(base[L], last) if kany else base[L]] = win(16 * L + first[0])
+    return stage, lead, f0, win
+
+
+def check_scatter(row, lo, hi, valid_upto):
+    kany = any(x >= 0xF0 for x in row[max(lo - 3, 0):hi])
+    edge = lo > 0 or hi < len(row)
+    for order in ("low", "high"):
+        stage, lead, f0, win = scatter_model(row, lo, hi, kany, order, edge)
+        s = 0
+        for i in range(valid_upto):
+            if lead[i]:
+                assert stage.get(s) == win(i), (order, i, s)
+                s += 1
+                if f0[i]:
+                    assert stage.get(s) == win(i) ^ 0x70, (order, i, s)
+                    s += 1
+
+
+def test_scatter_write_order():
+    from workloads import random_text, SCRIPT_MIXES
+    rng = np.random.default_rng(11)
+    mixes = ("mix1m",) + tuple(SCRIPT_MIXES)
+    for trial in range(48):
+        t = np.frombuffer(random_text(rng, mixes[trial % len(mixes)], 1200), dtype=np.uint8)
+        start = int(rng.integers(0, 4))
+        row = [int(x) for x in t[start:start + 1028]]
+        lo = 0 if trial % 3 else int(rng.integers(0, 40))
+        hi = 1028 if trial % 4 else int(rng.integers(900, 1028))
+        e = 1024
+        if trial % 2:   # an injected error: only the slots before it must hold
+            e = int(rng.integers(0, 1020))
+            kind = (trial // 2) % 4
+            if kind == 0:
+                row[e] = 0x80
+            elif kind == 1:
+                row[e] = 0xF8
+            elif kind == 2:
+                row[e:e + 8] = [0xF1] * 8
+            else:
+                row[e:e + 20] = [0x80] * 20
+            row = row[:1028]
+        check_scatter(row, lo, hi, max(min(e, hi) - 4, 0))
