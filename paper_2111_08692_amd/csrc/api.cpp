@@ -124,13 +124,13 @@ hipError_t get_ws(hipStream_t s, u64 ntiles, Workspace **out) {
         w->status = nullptr;
         w->status_cap = 0;
         u64 cap = ntiles < 4096 ? 4096 : ntiles + ntiles / 4;
-        if ((e = hipMalloc(&w->status, cap * sizeof(u64))) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(w->status, 0, cap * sizeof(u64), s)) != hipSuccess) return e;
+        if ((e = hipMalloc(&w->status, cap * kStatusStride * sizeof(u64))) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(w->status, 0, cap * kStatusStride * sizeof(u64), s)) != hipSuccess) return e;
         w->status_cap = cap;
     }
     if (ntiles > 0) {
         if (w->launches > 0 && w->launches % kClearEvery == 0) {
-            if ((e = hipMemsetAsync(w->status, 0, w->status_cap * sizeof(u64), s)) != hipSuccess) return e;
+            if ((e = hipMemsetAsync(w->status, 0, w->status_cap * kStatusStride * sizeof(u64), s)) != hipSuccess) return e;
         }
         w->launches++;
     }

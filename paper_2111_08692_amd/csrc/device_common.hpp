@@ -32,8 +32,8 @@
 namespace utfgpu {
 
 // Tiles of 32 KiB in workgroups of eight waves: two workgroups fit on a
-// CU (at up to 128 VGPRs), so one's load latency and look-back wait
-// overlap the other's work.
+// CU (the tile kernels are held to 128 VGPRs, four waves per SIMD), so
+// one's load latency and look-back wait overlap the other's work.
 constexpr int kWave = 64;
 constexpr int kWaves = 8;
 constexpr int kBlock = kWaves * kWave;             // 512 lanes
@@ -162,6 +162,10 @@ __device__ __forceinline__ uint32_t keep_range(uint32_t x, long long p, long lon
 // ------------------------------------------------------------------------
 // Decoupled look-back status words
 // ------------------------------------------------------------------------
+// Status words sit kStatusStride words apart, so the words a probe reads
+// spread over many memory channels instead of hammering a few lines.
+constexpr int kStatusStride = 32;   // 256 bytes
+
 constexpr u64 kFlagAggregate = 1ull;
 constexpr u64 kFlagPrefix = 2ull;
 constexpr u64 kEpochMask = (1ull << 22) - 1;
@@ -175,45 +179,73 @@ __device__ __forceinline__ bool status_ready(u64 s, u64 epoch) {
     return (s >> 62) != 0 && ((s >> 40) & kEpochMask) == (epoch & kEpochMask);
 }
 
-// Exclusive prefix of tile t (t > 0), run by one whole wave.  Lane j looks
-// at tile t-1-j.  The sum runs from the nearest predecessor that carries an
-// inclusive prefix, so only the tiles up to that one must have published;
-// if none of the 64 does, their aggregates are added and the window moves
-// back.  If a needed predecessor stays silent for `spin_limit` probes, the
-// wave computes its aggregate with `agg(tile)` (a wave-wide call returning
-// the same value in every lane) and publishes it unless the owner has done
-// so meanwhile.
+// Exclusive prefix of tile t (t > 0), run by one whole wave.  A probe
+// reads a window of kLookK * 64 predecessors: lane j looks at tiles
+// t-1-kLookK*j-k, k = 0..kLookK-1.  The sum runs from the nearest
+// predecessor that carries an inclusive prefix, so only the tiles up to
+// that one must have published; if none in the window does, their
+// aggregates are added and the window moves back.  Knowledge of prefixes
+// therefore advances one window per status round trip (about 1.5 us), so
+// the window, not the tile size alone, bounds how many tiles per second
+// the scan can serve.  If a needed predecessor stays silent for
+// `spin_limit` probes, the wave computes its aggregate with `agg(tile)` (a
+// wave-wide call returning the same value in every lane) and publishes it
+// unless the owner has done so meanwhile.
+constexpr int kLookK = 1;
+
 template <class Agg>
 __device__ __forceinline__ u64 lookback(u64 *status, long long t, u64 epoch, int spin_limit, Agg agg) {
     const uint32_t lane = lane_id();
     u64 excl = 0;
-    for (long long j = t - 1;; j -= kWave) {
-        const long long idx = j - (long long)lane;
-        u64 s = idx >= 0 ? ld_agent(status + idx) : pack_status(kFlagPrefix, epoch, 0);
+    for (long long j = t - 1;; j -= (long long)kLookK * kWave) {
+        const long long i0 = j - (long long)kLookK * lane;   // nearest tile of the lane
+        u64 s[kLookK];
+#pragma unroll
+        for (int k = 0; k < kLookK; ++k)
+            s[k] = i0 - k >= 0 ? ld_agent(status + (i0 - k) * kStatusStride) : pack_status(kFlagPrefix, epoch, 0);
         for (int spins = 0;;) {
-            const bool ready = idx < 0 || status_ready(s, epoch);
-            const u64 waiting = __ballot(!ready);
-            const u64 pmask = __ballot(ready && (s >> 62) == kFlagPrefix);
-            const u64 low = pmask & (~pmask + 1);                 // nearest prefix
+            // the lane's nearest prefix kp, whether a tile before it is not
+            // ready, the first such tile, and the sum up to the prefix
+            int kp = kLookK, fk = kLookK;
+            u64 lsum = 0;
+#pragma unroll
+            for (int k = 0; k < kLookK; ++k) {
+                const bool rdy = i0 - k < 0 || status_ready(s[k], epoch);
+                if (kp == kLookK) {
+                    if (!rdy && fk == kLookK) fk = k;
+                    if (rdy) {
+                        lsum += s[k] & kValueMask;
+                        if ((s[k] >> 62) == kFlagPrefix) kp = k;
+                    }
+                }
+            }
+            const u64 pmask = __ballot(kp < kLookK);
+            const u64 low = pmask & (~pmask + 1);                 // lane of the nearest prefix
             const u64 need = pmask ? (low << 1) - 1 : ~0ull;      // lanes up to it
-            const u64 blocking = waiting & need;
+            const u64 blocking = __ballot(fk < kLookK) & need;
             if (blocking == 0) {
-                const u64 v = ((need >> lane) & 1u) ? (s & kValueMask) : 0;
-                excl += wave_sum_u64(v);
+                excl += wave_sum_u64(((need >> lane) & 1u) ? lsum : 0);
                 if (pmask) return excl;
                 break;
             }
             if (spins >= spin_limit) {
-                const int k = __ffsll((long long)blocking) - 1;
-                const long long miss = j - k;
+                const int L = __ffsll((long long)blocking) - 1;
+                const int k = (int)readlane((uint32_t)fk, L);
+                const long long miss = j - (long long)kLookK * L - k;
                 const u64 a = agg(miss);
-                if ((int)lane == k) cas_agent(status + miss, s, pack_status(kFlagAggregate, epoch, a));
+                u64 old = s[0];
+#pragma unroll
+                for (int q = 1; q < kLookK; ++q)
+                    if (q == k) old = s[q];
+                if ((int)lane == L) cas_agent(status + miss * kStatusStride, old, pack_status(kFlagAggregate, epoch, a));
                 spins = 0;
             } else {
                 __builtin_amdgcn_s_sleep(2);
                 ++spins;
             }
-            if (!ready) s = ld_agent(status + idx);
+#pragma unroll
+            for (int k = 0; k < kLookK; ++k)
+                if (i0 - k >= 0 && !status_ready(s[k], epoch)) s[k] = ld_agent(status + (i0 - k) * kStatusStride);
         }
     }
 }
@@ -228,9 +260,9 @@ __device__ __forceinline__ u64 resolve_prefix(u64 *status, u64 t, u64 epoch, int
         if (lane == 0) st_agent(status, pack_status(kFlagPrefix, epoch, tile_total));
         return 0;
     }
-    if (lane == 0) st_agent(status + t, pack_status(kFlagAggregate, epoch, tile_total));
+    if (lane == 0) st_agent(status + t * kStatusStride, pack_status(kFlagAggregate, epoch, tile_total));
     const u64 prefix = lookback(status, (long long)t, epoch, spin_limit, agg);
-    if (lane == 0) st_agent(status + t, pack_status(kFlagPrefix, epoch, prefix + tile_total));
+    if (lane == 0) st_agent(status + t * kStatusStride, pack_status(kFlagPrefix, epoch, prefix + tile_total));
     return prefix;
 }
 
@@ -309,6 +341,106 @@ __device__ __forceinline__ void write_out_aligned(uint8_t *g0p, u64 nbytes, cons
             }
         }
     }
+}
+
+// ------------------------------------------------------------------------
+// Write-out of a wave's rows with the tail block carried over
+// ------------------------------------------------------------------------
+// A wave writes its output row by row from a stage laid out by 16-byte
+// blocks of global memory (the row's first byte g0 at stage byte g0 & 15).
+// The last block of a row is usually shared with the next row, so it is
+// not written but carried (16 bytes, the same in every lane) into the next
+// row's stage, whose block 0 it completes.  Only the wave's first and last
+// blocks are written in part; those take at most eight aligned stores of
+// 1/2/4/8 bytes (never below the unit size).
+struct Carry {
+    uint32_t v[4];
+};
+
+// Bytes [a, b) (both inside the 16-byte block at c) from stage bytes
+// [a - c + so, b - c + so), with aligned power-of-two stores.
+template <int kUnit>
+__device__ __forceinline__ void store_part(uintptr_t c, uintptr_t a, uintptr_t b, const uint8_t *sb, uint32_t so) {
+#pragma unroll
+    for (int sz = kUnit; sz <= 8; sz <<= 1) {   // up to the first 16-byte aligned chunk
+        if ((a & (uintptr_t)sz) && a + sz <= b) {
+            const uint32_t o = so + (uint32_t)(a - c);
+            if (sz == 1) *(uint8_t *)a = sb[o];
+            if (sz == 2) *(uint16_t *)a = *(const uint16_t *)(sb + o);
+            if (sz == 4) *(uint32_t *)a = *(const uint32_t *)(sb + o);
+            if (sz == 8) *(uint64_t *)a = *(const uint64_t *)(sb + o);
+            a += sz;
+        }
+    }
+#pragma unroll
+    for (int sz = 8; sz >= kUnit; sz >>= 1) {   // the rest, largest first
+        if (a + sz <= b) {
+            const uint32_t o = so + (uint32_t)(a - c);
+            if (sz == 1) *(uint8_t *)a = sb[o];
+            if (sz == 2) *(uint16_t *)a = *(const uint16_t *)(sb + o);
+            if (sz == 4) *(uint32_t *)a = *(const uint32_t *)(sb + o);
+            if (sz == 8) *(uint64_t *)a = *(const uint64_t *)(sb + o);
+            a += sz;
+        }
+    }
+}
+
+// Merge the carried block into block 0 of the next row's stage: its bytes
+// before g0 & 15 come from the carry.  Lane 0; an LDS sync follows.
+__device__ __forceinline__ void merge_carry(uint32_t *stage, uintptr_t g0, const Carry &cy, uint32_t lane) {
+    const uint32_t k = (uint32_t)(g0 & 15u);
+    if (lane == 0 && k != 0) {
+        u32x4 b = *(const u32x4 *)stage;
+        uint32_t m[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int lo = 4 * i;
+            m[i] = (int)k >= lo + 4 ? 0xFFFFFFFFu : ((int)k <= lo ? 0u : ((1u << (8 * ((int)k - lo))) - 1u));
+        }
+        b.x = (cy.v[0] & m[0]) | (b.x & ~m[0]);
+        b.y = (cy.v[1] & m[1]) | (b.y & ~m[1]);
+        b.z = (cy.v[2] & m[2]) | (b.z & ~m[2]);
+        b.w = (cy.v[3] & m[3]) | (b.w & ~m[3]);
+        *(u32x4 *)stage = b;
+    }
+}
+
+// Write a row's output [g0, g1) except its unfinished last block, which
+// goes to `cy`; bytes before `wstart` (the wave's first output byte) are
+// never written.  Whole wave; the stage holds the row, its block 0 merged
+// with the previous row's carry.
+template <int kUnit>
+__device__ __forceinline__ void write_row(uintptr_t g0, uintptr_t g1, uintptr_t wstart, const uint32_t *stage,
+                                          uint32_t lane, Carry &cy) {
+    const uintptr_t c0 = g0 & ~(uintptr_t)15;
+    const uintptr_t lo = c0 > wstart ? c0 : wstart;
+    const uintptr_t hi = g1 & ~(uintptr_t)15;
+    const uint8_t *sb = (const uint8_t *)stage;
+    if (hi > lo) {
+        for (uintptr_t c = c0 + 16 * (uintptr_t)lane; c < hi; c += 16 * kWave) {
+            const uint32_t so = (uint32_t)(c - c0);
+            if (c >= lo)
+                __builtin_nontemporal_store(*(const u32x4 *)(sb + so), (u32x4 *)c);
+            else
+                store_part<kUnit>(c, lo, c + 16, sb, so);
+        }
+    }
+    if (g1 & 15u) {   // every lane reads the same block
+        const u32x4 b = *(const u32x4 *)(sb + (uint32_t)(hi - c0));
+        cy.v[0] = b.x; cy.v[1] = b.y; cy.v[2] = b.z; cy.v[3] = b.w;
+    }
+}
+
+// The wave's last unfinished block: bytes [max(block, wstart), gend) from
+// the carry.  Lane 0 writes it through block 0 of the stage.
+template <int kUnit>
+__device__ __forceinline__ void flush_carry(uintptr_t gend, uintptr_t wstart, uint32_t *stage, const Carry &cy,
+                                            uint32_t lane) {
+    if (!(gend & 15u)) return;
+    const uintptr_t c = gend & ~(uintptr_t)15;
+    if (lane == 0) *(u32x4 *)stage = u32x4{cy.v[0], cy.v[1], cy.v[2], cy.v[3]};
+    wave_lds_sync();
+    if (lane == 0) store_part<kUnit>(c, c > wstart ? c : wstart, gend, (const uint8_t *)stage, 0);
 }
 
 // ------------------------------------------------------------------------

@@ -174,6 +174,27 @@ __device__ __forceinline__ uint32_t survey16(const LaneUnits &t, long long wbase
     return cls;
 }
 
+// Whether the lane's words hold an unpaired surrogate: word tests on the
+// words with their neighbours, no positions (words outside the input read as
+// zero, which pairs with nothing, as the end of the input does).
+__device__ __forceinline__ bool lane_has_unpaired(const LaneUnits &t, uint32_t lane) {
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        uint32_t u[10];
+        u[0] = prev_word(t, r, lane);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j + 1] = (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFC00u;
+        u[9] = next_word(t, r, lane);
+        u[0] &= 0xFC00u;
+        u[9] &= 0xFC00u;
+#pragma unroll
+        for (int j = 1; j <= 8; ++j)
+            bad |= (u[j] == 0xD800u && u[j + 1] != 0xDC00u) || (u[j] == 0xDC00u && u[j - 1] != 0xD800u);
+    }
+    return bad;
+}
+
 // First unpaired surrogate among the lane's words (position << 4 | kind).
 __device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, long long wbase, long long head,
                                                   long long end, uint32_t lane) {
@@ -199,33 +220,37 @@ __device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, long long 
     return ~0ull;
 }
 
-// UTF-8 bytes of word u (first byte lowest) and their number; `pv` and
-// `nx` are the words before and after (used by surrogates).  No branches.
+// UTF-8 bytes of word u: b0, b1, b2 in output order (only the low byte of
+// each is meaningful) and their number; `pv` and `nx` are the words before
+// and after (used by surrogates).  No branches.
 template <uint32_t kClass>
-__device__ __forceinline__ uint32_t encode_word(uint32_t u, uint32_t pv, uint32_t nx, uint32_t &len) {
-    const uint32_t c1 = u >= 0x80u, c2 = u >= 0x800u;
-    const uint32_t t0 = 0x80u | (u & 0x3Fu);
-    uint32_t e2 = (0xC0u | (u >> 6)) | (t0 << 8);
+__device__ __forceinline__ void encode_word(uint32_t u, uint32_t pv, uint32_t nx, uint32_t &b0, uint32_t &b1,
+                                            uint32_t &b2, uint32_t &len) {
+    const bool c1 = u >= 0x80u;
+    const uint32_t t6 = u >> 6;
+    const uint32_t last = (u & 0x3Fu) | 0x80u;            // last byte of a 2- or 3-byte sequence
+    b0 = c1 ? (t6 | 0xC0u) : u;                           // 2-byte lead (or the ASCII byte)
+    b1 = last;
+    b2 = last;
     if (kClass == kUpTo2B) {
         len = 1u + c1;
-        return c1 ? e2 : u;
+        return;
     }
-    uint32_t e3 = (0xE0u | (u >> 12)) | ((0x80u | ((u >> 6) & 0x3Fu)) << 8) | (t0 << 16);
-    asm volatile("" : "+v"(e2), "+v"(e3));   // selects, not branches
-    const uint32_t e = c2 ? e3 : (c1 ? e2 : u);
-    if (kClass == kBmp) {
-        len = 1u + c1 + c2;
-        return e;
-    }
+    const bool c2 = u >= 0x800u;
+    b0 = c2 ? ((u >> 12) | 0xE0u) : b0;
+    b1 = c2 ? ((t6 & 0x3Fu) | 0x80u) : b1;
+    len = 1u + c1 + c2;
+    if (kClass == kBmp) return;
     // surrogates: the high word writes F0|.., 80|.. of the pair's code
     // point, the low word the last two bytes
-    const bool hi = is_high(u), sur = is_sur(u);
-    const uint32_t cp = 0x10000u + ((((hi ? u : pv) & 0x3FFu) << 10) | ((hi ? nx : u) & 0x3FFu));
-    uint32_t sh = (0xF0u | (cp >> 18)) | ((0x80u | ((cp >> 12) & 0x3Fu)) << 8);
-    uint32_t sl = (0x80u | ((cp >> 6) & 0x3Fu)) | ((0x80u | (cp & 0x3Fu)) << 8);
-    asm volatile("" : "+v"(sh), "+v"(sl));
-    len = sur ? 2u : 1u + c1 + c2;
-    return sur ? (hi ? sh : sl) : e;
+    const bool hi = (u & 0xFC00u) == 0xD800u, sur = (u & 0xF800u) == 0xD800u;
+    const uint32_t h10 = (hi ? u : pv) & 0x3FFu, l10 = (hi ? nx : u) & 0x3FFu;
+    const uint32_t cp = 0x10000u + ((h10 << 10) | l10);
+    const uint32_t s0 = hi ? ((cp >> 18) | 0xF0u) : (((cp >> 6) & 0x3Fu) | 0x80u);
+    const uint32_t s1 = hi ? (((cp >> 12) & 0x3Fu) | 0x80u) : ((cp & 0x3Fu) | 0x80u);
+    b0 = sur ? s0 : b0;
+    b1 = sur ? s1 : b1;
+    len = sur ? 2u : len;
 }
 
 // Word j of the lane's chunk of row r, with j = -1 and j = 8 the words
@@ -237,54 +262,52 @@ __device__ __forceinline__ uint32_t word_of(const LaneUnits &t, int r, int j, ui
 }
 
 // Encode the lane's chunk of row r into the stage at byte offset o, then
-// rewrite the lane's first two bytes.
-template <uint32_t kClass>
+// rewrite the lane's first two bytes.  kEdge: the wave reaches outside the
+// input, whose words encode to nothing.
+template <uint32_t kClass, bool kEdge>
 __device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o, uint8_t *st, long long wbase,
                                            long long head, long long end, uint32_t lane) {
     const uint32_t pv = kClass == kAnyUnit ? prev_word(t, r, lane) : 0u;
     const uint32_t nx = kClass == kAnyUnit ? next_word(t, r, lane) : 0u;
-    const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+    uint32_t in = 0xFFu;   // words of the chunk inside the input
+    if (kEdge) {
+        const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+        in = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (q0 + j >= head && q0 + j < end) in |= 1u << j;
+    }
     const uint32_t o0 = o;
-    uint32_t e0 = 0, e1 = 0, l0 = 0;
+    uint32_t first = 0, nfirst = 0;   // the lane's first two output bytes
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        uint32_t len;
-        const uint32_t e = encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx),
-                                               word_of(t, r, j + 1, pv, nx), len);
-        if (t.edge && (q0 + j < head || q0 + j >= end)) len = 0;
-        st[o] = (uint8_t)e;
-        st[o + 1] = (uint8_t)(e >> 8);
-        st[o + 2] = (uint8_t)(e >> 16);
-        if (j == 0) {
-            e0 = e;
-            l0 = len;
-        }
-        if (j == 1) e1 = e;
-        o += len;
-    }
-    wave_lds_sync();   // every lane's stores land before the rewrite
-    uint32_t first, nfirst;
-    if (!t.edge) {
-        first = l0 >= 2u ? (e0 & 0xFFFFu) : ((e0 & 0xFFu) | ((e1 & 0xFFu) << 8));
-        nfirst = 2;
-    } else {
-        first = 0;
-        nfirst = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            uint32_t len;
-            const uint32_t e = encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx),
-                                                   word_of(t, r, j + 1, pv, nx), len);
-            if (q0 + j < head || q0 + j >= end) len = 0;
+        uint32_t b0, b1, b2, len;
+        encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx), word_of(t, r, j + 1, pv, nx),
+                            b0, b1, b2, len);
+        if (kEdge && !((in >> j) & 1u)) len = 0;
+        st[o] = (uint8_t)b0;
+        st[o + 1] = (uint8_t)b1;
+        if (kClass != kUpTo2B) st[o + 2] = (uint8_t)b2;
+        if (!kEdge) {
+            if (j == 0) {
+                first = (b0 & 0xFFu) | ((b1 & 0xFFu) << 8);
+                nfirst = len;
+            }
+            if (j == 1 && nfirst == 1u) first = (first & 0xFFu) | ((b0 & 0xFFu) << 8);
+        } else {
+            const uint32_t bytes = (b0 & 0xFFu) | ((b1 & 0xFFu) << 8) | ((b2 & 0xFFu) << 16);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if ((uint32_t)k < len && nfirst < 2u) {
-                    first |= ((e >> (8 * k)) & 0xFFu) << (8 * nfirst);
+                    first |= ((bytes >> (8 * k)) & 0xFFu) << (8 * nfirst);
                     ++nfirst;
                 }
             }
         }
+        o += len;
     }
+    if (!kEdge) nfirst = 2;   // every word has at least one byte
+    wave_lds_sync();          // every lane's stores land before the rewrite
     if (nfirst >= 1u) st[o0] = (uint8_t)first;
     if (nfirst >= 2u) st[o0 + 1] = (uint8_t)(first >> 8);
 }
@@ -310,7 +333,7 @@ __device__ __forceinline__ void narrow_row(const LaneUnits &t, int r, uint32_t s
 }
 
 template <bool kConvert>
-__global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__restrict__ frame, long long head,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(const uint8_t *__restrict__ frame, long long head,
                                                              long long m, uint8_t *__restrict__ out, u64 out_cap,
                                                              u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
                                                              u64 ntiles, int spin_limit) {
@@ -331,6 +354,12 @@ __global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__res
     uint32_t width[kRows];
     uint32_t cls = survey16<kConvert>(t, wbase, head, end, lane, width);
     if (cls == kAscii16 && t.edge) cls = kUpTo2B;   // whole-chunk narrowing: not at the ends
+
+    // a wave holding an unpaired surrogate; when an error before it is
+    // already known, its output (past the valid prefix) is not written and
+    // its first error not located
+    const bool unpaired = cls == kAnyUnit && __ballot(lane_has_unpaired(t, lane)) != 0;
+    const bool moot = unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
 
     if (kConvert) {
         uint32_t off[kRows], rowbase[kRows + 1];
@@ -367,27 +396,43 @@ __global__ __launch_bounds__(kBlock) void utf16_tile_kernel(const uint8_t *__res
         uint32_t *wst = stage + wave * kStageWords16;
         uint8_t *wst8 = (uint8_t *)wst;
         const u64 base = s_prefix + wave_off;
+        const uintptr_t wstart = (uintptr_t)(out + (base < out_cap ? base : out_cap));
+        uintptr_t gend = wstart;   // end of the bytes written or carried so far
+        Carry cy = {{0u, 0u, 0u, 0u}};
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < kRows && !moot; ++r) {
             const u64 b0 = base + rowbase[r];
-            const uint32_t s = (uint32_t)((uintptr_t)(out + b0) & 15u);
-            switch (cls) {
-                case kAscii16: narrow_row(t, r, s, wst, lane); break;
-                case kUpTo2B: encode_row<kUpTo2B>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
-                case kBmp: encode_row<kBmp>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
-                default: encode_row<kAnyUnit>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+            u64 b1 = base + rowbase[r + 1];
+            if (b1 > out_cap) b1 = out_cap;
+            if (b0 >= b1) continue;   // an empty row, or nothing of it fits
+            const uintptr_t g0 = (uintptr_t)(out + b0), g1 = (uintptr_t)(out + b1);
+            const uint32_t s = (uint32_t)(g0 & 15u);
+            if (!t.edge) {
+                switch (cls) {
+                    case kAscii16: narrow_row(t, r, s, wst, lane); break;
+                    case kUpTo2B: encode_row<kUpTo2B, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    case kBmp: encode_row<kBmp, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    default: encode_row<kAnyUnit, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                }
+            } else {   // waves at the ends of the input (never all-ASCII)
+                switch (cls) {
+                    case kUpTo2B: encode_row<kUpTo2B, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    case kBmp: encode_row<kBmp, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    default: encode_row<kAnyUnit, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                }
             }
             wave_lds_sync();
-            u64 nbytes = rowbase[r + 1] - rowbase[r];
-            if (b0 >= out_cap) nbytes = 0;
-            else if (b0 + nbytes > out_cap) nbytes = out_cap - b0;
-            write_out_aligned<1, kWave>(out + b0, nbytes, wst, lane);
+            if (gend > wstart) merge_carry(wst, g0, cy, lane);
+            wave_lds_sync();
+            write_row<1>(g0, g1, wstart, wst, lane, cy);
+            gend = g1;
             wave_lds_sync();
         }
+        if (!moot) flush_carry<1>(gend, wstart, wst, cy, lane);
     }
 
     // the first unpaired surrogate, unless an error before the wave is known
-    if (cls == kAnyUnit && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
+    if (unpaired && !moot && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
         u64 err = lane_first_error16(t, wbase, head, end, lane);
         err = wave_min_u64(err);
         if (lane == 0 && err != ~0ull) min_agent(&ctrl->err, err);

@@ -461,32 +461,46 @@ __device__ __forceinline__ void widen_store_wave(const LaneBytes &t, uint16_t *o
 }
 
 // The wave's conversion after the tile prefix is known.  `staged0`: group
-// 0 has been staged already.  Returns whether a value rule failed.
+// 0 has been staged already.  Returns whether a value rule failed.  Rows
+// are written with their unfinished last block carried to the next row.
 template <uint32_t kClass>
 __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
                                              const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
                                              u64 out_cap, uint32_t *wst, long long wbase, long long head,
                                              long long end, uint32_t lane, bool staged0) {
     bool bad = false;
+    uintptr_t wlo = (uintptr_t)(out + (base < out_cap ? base : out_cap));   // lowest byte this wave writes
+    uintptr_t gend = wlo;                                                  // end of the bytes done so far
+    Carry cy = {{0u, 0u, 0u, 0u}};
 #pragma unroll
     for (int g = 0; g < kRows / kGroup; ++g) {
+        const u64 u0 = base + rowbase[g * kGroup];
+        uint32_t nslots = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
+        if (nslots > kStageSlots) nslots = kStageSlots;   // only past an error
+        u64 u1 = u0 + nslots;
+        if (u1 > out_cap) u1 = out_cap;
+        const uintptr_t g0 = (uintptr_t)(out + u0), g1 = (uintptr_t)(out + u1);
+        if (u0 < u1 && gend != g0) {   // a row cut short before (past an error): finish its block
+            flush_carry<2>(gend, wlo, wst, cy, lane);
+            wlo = gend;
+        }
         if (g > 0 || !staged0)
 #pragma unroll
             for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
                 scatter_row<kClass>(t, r, gof[r], wst, wbase, head, end, lane);
         wave_lds_sync();
-        const u64 u0 = base + rowbase[g * kGroup];
-        uint32_t nslots = rowbase[(g + 1) * kGroup] - rowbase[g * kGroup];
-        if (nslots > kStageSlots) nslots = kStageSlots;   // only past an error
         const uint32_t h = (uint32_t)(((uintptr_t)(out + u0) >> 1) & 7u);
-        bad |= decode_slots<kClass>(wst, nslots, h, lane);
-        wave_lds_sync();
-        u64 nunits = nslots;
-        if (u0 >= out_cap) nunits = 0;
-        else if (u0 + nunits > out_cap) nunits = out_cap - u0;
-        write_out_aligned<2, kWave>((uint8_t *)(out + u0), 2 * nunits, wst, lane);
+        bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
+        if (u0 < u1) {
+            wave_lds_sync();
+            if (gend == g0 && gend > wlo) merge_carry(wst, g0, cy, lane);
+            wave_lds_sync();
+            write_row<2>(g0, g1, wlo, wst, lane, cy);
+            gend = g1;
+        }
         wave_lds_sync();
     }
+    flush_carry<2>(gend, wlo, wst, cy, lane);
     return bad;
 }
 
@@ -583,7 +597,7 @@ __device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) 
 // Validation and conversion: tile t = workgroup t.
 // ------------------------------------------------------------------------
 template <bool kConvert>
-__global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__restrict__ frame, long long head,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf8_tile_kernel(const uint8_t *__restrict__ frame, long long head,
                                                             long long n, uint16_t *__restrict__ out, u64 out_cap,
                                                             u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
                                                             u64 ntiles, int spin_limit) {
@@ -608,6 +622,9 @@ __global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__rest
         const uint32_t cls = (sv.cls == kAscii && t.edge) ? kUpTo2 : sv.cls;
         bool flag = sv.mis;
         fence_values(t);
+        // a wave whose detector fired, when an error before it is already
+        // known: its output lies past the valid prefix and is not written
+        const bool moot = kConvert && __ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
 
         if (kConvert) {
             // in-wave offsets (row-major) and wave total
@@ -644,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__rest
                 }
             }
             uint32_t *wst = stage + wave * kStageWords;
-            switch (cls) {   // the first group needs no prefix
+            if (!moot) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
                 case kUpTo2: scatter_row<kUpTo2>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 case kUpTo3: scatter_row<kUpTo3>(t, 0, gof[0], wst, wbase, head, end, lane); break;
@@ -652,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void utf8_tile_kernel(const uint8_t *__rest
             }
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
-            switch (cls) {
+            if (!moot) switch (cls) {
                 case kAscii:
                     if (base + kWaveBytes <= out_cap)
                         widen_store_wave(t, out, base, lane);
