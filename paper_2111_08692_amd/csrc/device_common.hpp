@@ -191,7 +191,7 @@ __device__ __forceinline__ bool status_ready(u64 s, u64 epoch) {
 // `spin_limit` probes, the wave computes its aggregate with `agg(tile)` (a
 // wave-wide call returning the same value in every lane) and publishes it
 // unless the owner has done so meanwhile.
-constexpr int kLookK = 1;
+constexpr int kLookK = 2;
 
 template <class Agg>
 __device__ __forceinline__ u64 lookback(u64 *status, long long t, u64 epoch, int spin_limit, Agg agg) {
@@ -240,7 +240,7 @@ __device__ __forceinline__ u64 lookback(u64 *status, long long t, u64 epoch, int
                 if ((int)lane == L) cas_agent(status + miss * kStatusStride, old, pack_status(kFlagAggregate, epoch, a));
                 spins = 0;
             } else {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(4);
                 ++spins;
             }
 #pragma unroll
@@ -425,9 +425,12 @@ __device__ __forceinline__ void write_row(uintptr_t g0, uintptr_t g1, uintptr_t 
                 store_part<kUnit>(c, lo, c + 16, sb, so);
         }
     }
-    if (g1 & 15u) {   // every lane reads the same block
+    if (g1 & 15u) {   // every lane reads the same block; kept in scalar registers
         const u32x4 b = *(const u32x4 *)(sb + (uint32_t)(hi - c0));
-        cy.v[0] = b.x; cy.v[1] = b.y; cy.v[2] = b.z; cy.v[3] = b.w;
+        cy.v[0] = __builtin_amdgcn_readfirstlane(b.x);
+        cy.v[1] = __builtin_amdgcn_readfirstlane(b.y);
+        cy.v[2] = __builtin_amdgcn_readfirstlane(b.z);
+        cy.v[3] = __builtin_amdgcn_readfirstlane(b.w);
     }
 }
 

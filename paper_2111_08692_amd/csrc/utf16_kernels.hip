@@ -67,8 +67,9 @@ __device__ __forceinline__ void load_span16(const uint8_t *frame, long long head
     t.hn = 0;
     if (wbase - 2 >= 0 && wbase - 2 < end) t.hp = *(const uint32_t *)(frame + 2 * (wbase - 2));
     if (wbase + kWaveUnits < end) t.hn = *(const uint32_t *)(frame + 2 * (wbase + kWaveUnits));
-    t.hp = keep_units(t.hp, wbase - 2, head, end);
-    t.hn = keep_units(t.hn, wbase + kWaveUnits, head, end);
+    // the same dwords in every lane: scalar registers
+    t.hp = __builtin_amdgcn_readfirstlane(keep_units(t.hp, wbase - 2, head, end));
+    t.hn = __builtin_amdgcn_readfirstlane(keep_units(t.hn, wbase + kWaveUnits, head, end));
     t.edge = wbase < head || wbase + kWaveUnits > end;
     if (t.edge) {
 #pragma unroll

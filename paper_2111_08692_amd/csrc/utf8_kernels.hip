@@ -33,7 +33,11 @@
 namespace utfgpu {
 
 // Byte class of a wave, over its own bytes and the three bytes before it.
-enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kAny = 3 };
+// kQuad: leading bytes only below 0x80 or from F0 on (ASCII text with
+// four-byte characters, e.g. emoji), a decode without the 2- and 3-byte forms.
+enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kQuad = 3, kAny = 4 };
+// Classes whose waves can hold four-byte characters (two slots each).
+constexpr bool has4(uint32_t cls) { return cls >= kQuad; }
 
 // Slots one wave stages at a time (kGroup rows).  Valid input needs at most
 // one slot per byte of the group plus one: a group can end with the leading
@@ -124,8 +128,9 @@ __device__ __forceinline__ void issue_span(const uint8_t *frame, long long end, 
 // Zero everything outside [head, end) once the loads have arrived.
 __device__ __forceinline__ void finish_span(long long head, long long end, long long wbase, uint32_t lane,
                                             LaneBytes &t) {
-    t.hp = keep_range(t.hp, wbase - 4, head, end);
-    t.hn = keep_range(t.hn, wbase + kWaveBytes, head, end);
+    // the same dwords in every lane: scalar registers
+    t.hp = __builtin_amdgcn_readfirstlane(keep_range(t.hp, wbase - 4, head, end));
+    t.hn = __builtin_amdgcn_readfirstlane(keep_range(t.hn, wbase + kWaveBytes, head, end));
     t.edge = wbase < head || wbase + kWaveBytes > end;
     if (t.edge) {
 #pragma unroll
@@ -181,6 +186,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
     }
     uint32_t aE0 = lane == 0 ? ge_e0(t.hp & 0xFFFFFF00u) : 0u;
     uint32_t aF0 = lane == 0 ? ge_f0(t.hp & 0xFFFFFF00u) : 0u;
+    uint32_t aMid = 0;   // own bytes C0..EF
     uint32_t mis = 0;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
@@ -199,6 +205,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
             mis |= (must & 0x80808080u) ^ cont_bits(x);
             aE0 |= e0;
             aF0 |= f0;
+            aMid |= c0 & ~f0;
             w = w - __popc(cb) + __popc(f0 & 0x80808080u);
             pc0 = c0;
             pe0 = e0;
@@ -207,7 +214,10 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
         sv.width[r] = w;
     }
     sv.mis = mis != 0;
-    sv.cls = __ballot((aF0 & 0x80808080u) != 0) ? kAny : (__ballot((aE0 & 0x80808080u) != 0) ? kUpTo3 : kUpTo2);
+    if (__ballot((aF0 & 0x80808080u) != 0))
+        sv.cls = __ballot((aMid & 0x80808080u) != 0) ? kAny : kQuad;
+    else
+        sv.cls = __ballot((aE0 & 0x80808080u) != 0) ? kUpTo3 : kUpTo2;
 }
 
 // Output width (UTF-16 words) of one 16-byte chunk given its bytes and its
@@ -276,15 +286,15 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
         const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
         const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
         if (j == 0) lead0 = lead;
-        const uint32_t f0 = kClass == kAny ? ge_f0(x) & 0x80808080u : 0u;
+        const uint32_t f0 = has4(kClass) ? ge_f0(x) & 0x80808080u : 0u;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t win = window4(x, nx, k);
-            const uint32_t a = kClass == kAny ? min(o, kLast) : o;
-            const uint32_t fb = kClass == kAny ? __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1) << 2 : 0u;
+            const uint32_t a = has4(kClass) ? min(o, kLast) : o;
+            const uint32_t fb = has4(kClass) ? __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1) << 2 : 0u;
             // the marked copy goes to the next slot for a four-byte leading
             // byte, else to this slot, where the plain window replaces it
-            if (kClass == kAny) *(uint32_t *)(sb + a + fb) = win ^ 0x70u;
+            if (has4(kClass)) *(uint32_t *)(sb + a + fb) = win ^ 0x70u;
             *(uint32_t *)(sb + a) = win;
             o += (__builtin_amdgcn_ubfe(lead, 8 * k + 7, 1) << 2) + fb;
         }
@@ -310,7 +320,7 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
         win = __builtin_amdgcn_alignbyte(hi, lo, p & 3u);
     }
     if (has) {
-        const uint32_t a = kClass == kAny ? min(4u * gof, kLast) : 4u * gof;
+        const uint32_t a = has4(kClass) ? min(4u * gof, kLast) : 4u * gof;
         *(uint32_t *)(sb + a) = win;
     }
 }
@@ -333,6 +343,18 @@ __device__ __forceinline__ uint32_t decode_word(uint32_t w, bool &bad) {
         opaque(c2, c2);
         bad |= (w & 0xFEu) == 0xC0u;                          // C0, C1: overlong
         return b0 >= 0xC0u ? c2 : b0;
+    }
+    if (kClass == kQuad) {
+        const bool low = (w & 0xC0u) == 0x80u;                 // marked low-surrogate copy
+        w ^= low ? 0x70u : 0u;
+        const uint32_t b0 = w & 0xFFu;
+        const uint32_t c4 = ((w & 0x0Fu) << 18) | (((w >> 8) & 0x3Fu) << 12) | (((w >> 16) & 0x3Fu) << 6) |
+                            ((w >> 24) & 0x3Fu);
+        // rule 1 (F8..FF) lands above U+10FFFF through the fourth payload bit
+        bad |= (b0 >= 0x80u) & (c4 - 0x10000u > 0xFFFFFu);
+        uint32_t hi = 0xD7C0u + (c4 >> 10), lo = 0xDC00u | (c4 & 0x3FFu);
+        opaque(hi, lo);
+        return b0 < 0x80u ? b0 : (low ? lo : hi);
     }
     bool low = false;
     if (kClass == kAny) {
@@ -665,6 +687,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 case kAscii: break;
                 case kUpTo2: scatter_row<kUpTo2>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 case kUpTo3: scatter_row<kUpTo3>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                case kQuad: scatter_row<kQuad>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 default: scatter_row<kAny>(t, 0, gof[0], wst, wbase, head, end, lane); break;
             }
             __syncthreads();   // the tile prefix is known
@@ -684,6 +707,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 case kUpTo3:
                     flag |= convert_wave<kUpTo3>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                                  true);
+                    break;
+                case kQuad:
+                    flag |= convert_wave<kQuad>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                                                true);
                     break;
                 default:
                     flag |= convert_wave<kAny>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
