@@ -68,6 +68,11 @@ __device__ __forceinline__ uint32_t lead_kind(uint32_t b0, uint32_t b1, uint32_t
     return kOk;
 }
 
+// Bit 7 of every zero byte of t.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t t) {
+    return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+}
+
 // Bit 7 of every byte: byte >= C0, >= E0, >= F0; continuation.
 __device__ __forceinline__ uint32_t ge_c0(uint32_t x) { return x & (x << 1); }
 __device__ __forceinline__ uint32_t ge_e0(uint32_t x) { return x & (x << 1) & (x << 2); }
@@ -482,6 +487,91 @@ __device__ __forceinline__ void widen_store_wave(const LaneBytes &t, uint16_t *o
     }
 }
 
+// ------------------------------------------------------------------------
+// Waves of 1- and 2-byte characters: words computed at every position
+// ------------------------------------------------------------------------
+// The word of the character that starts at a byte is the byte itself
+// (ASCII), or for C0..DF its five payload bits above the next byte's six;
+// SWAR computes it at all four positions of a dword as two packed 16-bit
+// halves (even positions, odd positions).  Every position then stores its
+// word, in position order, at the slot of the next leading byte -- the
+// order rule of the window scatter above -- so no decode pass is needed.
+__device__ __forceinline__ void words2(uint32_t x, uint32_t nx, uint32_t &ce, uint32_t &co) {
+    const uint32_t c0 = ge_c0(x) & 0x80808080u;               // leading bytes C0..DF
+    const uint32_t p = x & ~(c0 >> 1) & 0x7F7F7F7Fu;           // payload of a leading byte
+    const uint32_t q = __builtin_amdgcn_alignbyte(nx, x, 1) & 0x3F3F3F3Fu;   // payload of the next byte
+    const uint32_t m = (c0 << 1) - (c0 >> 7);                  // 0xFF for the bytes C0..DF
+    const uint32_t pe = __builtin_amdgcn_perm(0u, p, 0x0c020c00u), qe = __builtin_amdgcn_perm(0u, q, 0x0c020c00u);
+    const uint32_t po = __builtin_amdgcn_perm(0u, p, 0x0c030c01u), qo = __builtin_amdgcn_perm(0u, q, 0x0c030c01u);
+    const uint32_t me = __builtin_amdgcn_perm(0u, m, 0x02020000u), mo = __builtin_amdgcn_perm(0u, m, 0x03030101u);
+    ce = (me & ((pe << 6) | qe)) | (~me & pe);
+    co = (mo & ((po << 6) | qo)) | (~mo & po);
+}
+
+// Word at position k (0..3) of a dword from its packed halves.
+__device__ __forceinline__ uint32_t word_at2(uint32_t ce, uint32_t co, uint32_t k) {
+    return ((k & 1u) ? co : ce) >> (16 * (k >> 1));
+}
+
+// Bit 7 of every C0 / C1 byte (overlong two-byte leads).
+__device__ __forceinline__ uint32_t overlong2_bits(uint32_t x) {
+    return zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);
+}
+
+// Stage the lane's chunk of row r: words at halfword o + slot.  Returns
+// whether a value rule failed (C0 or C1 leading byte).
+__device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
+                                               long long head, long long end, uint32_t lane) {
+    uint16_t *st16 = (uint16_t *)wst;
+    const uint32_t nx_row = next_dword(t, r, lane);
+    const uint32_t o0 = o;
+    uint32_t bad = 0, ce0 = 0, co0 = 0, lead0 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t x = t.d[r][j];
+        const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
+        const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+        uint32_t ce, co;
+        words2(x, nx, ce, co);
+        bad |= overlong2_bits(x);
+        if (j == 0) {
+            ce0 = ce;
+            co0 = co;
+            lead0 = lead;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            st16[o] = (uint16_t)word_at2(ce, co, (uint32_t)k);
+            o += __builtin_amdgcn_ubfe(lead, 8 * k + 7, 1);
+        }
+    }
+    // rewrite the first slot (see scatter_row)
+    uint32_t v = 0;
+    bool has;
+    if (!t.edge) {
+        has = lead0 != 0;
+        v = word_at2(ce0, co0, (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3);
+    } else {
+        uint32_t p = 16;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+            if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
+        }
+        has = p < 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if ((p >> 2) == (uint32_t)j) {
+                uint32_t ce, co;
+                words2(t.d[r][j], j < 3 ? t.d[r][j + 1] : nx_row, ce, co);
+                v = word_at2(ce, co, p & 3u);
+            }
+        }
+    }
+    if (has) st16[o0] = (uint16_t)v;
+    return bad != 0;
+}
+
 // The wave's conversion after the tile prefix is known.  `staged0`: group
 // 0 has been staged already.  Returns whether a value rule failed.  Rows
 // are written with their unfinished last block carried to the next row.
@@ -506,13 +596,19 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
             flush_carry<2>(gend, wlo, wst, cy, lane);
             wlo = gend;
         }
-        if (g > 0 || !staged0)
+        const uint32_t h = (uint32_t)(((uintptr_t)(out + u0) >> 1) & 7u);
+        if (kClass == kUpTo2) {   // words straight from the bytes
 #pragma unroll
             for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
-                scatter_row<kClass>(t, r, gof[r], wst, wbase, head, end, lane);
-        wave_lds_sync();
-        const uint32_t h = (uint32_t)(((uintptr_t)(out + u0) >> 1) & 7u);
-        bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
+                bad |= scatter_words2(t, r, h + gof[r], wst, wbase, head, end, lane);
+        } else {
+            if (g > 0 || !staged0)
+#pragma unroll
+                for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
+                    scatter_row<kClass>(t, r, gof[r], wst, wbase, head, end, lane);
+            wave_lds_sync();
+            bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
+        }
         if (u0 < u1) {
             wave_lds_sync();
             if (gend == g0 && gend > wlo) merge_carry(wst, g0, cy, lane);
@@ -530,11 +626,6 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
 // Validation only: value rules on every leading byte, from its byte and
 // the next (SWAR over the dword x, with y = the bytes one position later).
 // ------------------------------------------------------------------------
-// Bit 7 of every zero byte of t.
-__device__ __forceinline__ uint32_t zero_bytes(uint32_t t) {
-    return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
-}
-
 template <uint32_t kClass>
 __device__ __forceinline__ uint32_t value_bits(uint32_t x, uint32_t y) {
     uint32_t bad = zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);            // C0, C1
@@ -685,7 +776,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             uint32_t *wst = stage + wave * kStageWords;
             if (!moot) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
-                case kUpTo2: scatter_row<kUpTo2>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 case kUpTo3: scatter_row<kUpTo3>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 case kQuad: scatter_row<kQuad>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 default: scatter_row<kAny>(t, 0, gof[0], wst, wbase, head, end, lane); break;
