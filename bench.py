@@ -155,6 +155,60 @@ def one_mib_latency(G, small, dev, stream, res, aux):
     aux["mix1m_8to16_kernel_input_GBps"] = round(small.data.size / kt / 1e9, 1)
 
 
+def batch_leg(G, dev, stream, aux):
+    """The batched workload: 100 000 independent UTF-8 strings (log-normal
+    lengths, median 256 B, sigma 1.5, 16 B .. 1 MiB, one script mix each,
+    1% with one injected error) converted by one batched call, against the
+    same strings converted by one asynchronous single-buffer call each."""
+    import torch
+    from workloads.mixes import make_batch
+    b = make_batch()
+    k = b.offsets.size - 1
+    d = torch.from_numpy(b.data).to(dev)
+    offs = torch.from_numpy(b.offsets).to(dev)
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    G.utf16_length_from_utf8_async(d, tot)
+    total = int(tot.item())
+    out = torch.empty(max(total, 1), dtype=torch.int16, device=dev)
+    oo = torch.empty(k + 1, dtype=torch.int64, device=dev)
+    rs = G.results_tensor(k, device=dev)
+    for _ in range(3):
+        assert G.convert_utf8_to_utf16le_batch_async(d, offs, out, oo, rs) == 0
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for s_, e_ in ev:
+        s_.record(stream)
+        G.convert_utf8_to_utf16le_batch_async(d, offs, out, oo, rs)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    t = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
+    st, cnt = G.decode_results(rs, k)
+    ooff = oo.cpu().numpy()
+    err = np.zeros(k, dtype=bool)
+    err[list(b.errors)] = True
+    assert np.all(st[~err] == 0) and np.array_equal(cnt[~err], np.diff(ooff)[~err]), "batch results"
+    assert np.all((st[err] >= 1) & (st[err] <= 6)), "batch error kinds"
+    assert np.array_equal(cnt[err], np.array([b.errors[i] for i in np.nonzero(err)[0]])), "batch error offsets"
+    # the same strings, one asynchronous single-buffer call each
+    res1 = torch.zeros((k, 2), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(k):
+        a, e = int(b.offsets[i]), int(b.offsets[i + 1])
+        G.convert_utf8_to_utf16le_async(d[a:e], out[int(ooff[i]):], res1[i], out_cap=int(ooff[i + 1] - ooff[i]))
+    torch.cuda.synchronize()
+    tloop = time.perf_counter() - t0
+    alg = b.data.size + 2 * total
+    aux["batch100k_workload"] = (f"{k} UTF-8 strings, {b.data.size} bytes, log-normal lengths (median 256 B, "
+                                 "sigma 1.5, 16 B..1 MiB), one script mix each, 1% with one error")
+    aux["batch100k_call_ms"] = round(t * 1e3, 3)
+    aux["batch100k_input_GBps"] = round(b.data.size / t / 1e9, 1)
+    aux["batch100k_strings_per_s"] = round(k / t, 0)
+    aux["batch100k_roofline_frac"] = round(alg / t / 1e9 / HBM_PEAK_GBS, 3)
+    aux["batch100k_single_calls_ms"] = round(tloop * 1e3, 1)
+    aux["batch100k_speedup_vs_single_calls"] = round(tloop / t, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +374,8 @@ def main():
     # the 1 MiB single buffer: latency of one synchronous call
     if not args.no_aux:
         one_mib_latency(G, small, dev, stream, res, aux)
+        log("batched strings")
+        batch_leg(G, dev, stream, aux)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(bufs, args.cpu_sample_mib << 20)
 

@@ -74,12 +74,15 @@ enum {
     UTF_ERR_NULL = -1,
     UTF_ERR_ALIGN = -2,
     UTF_ERR_TOO_BIG = -3,
-    UTF_ERR_HIP = -4
+    UTF_ERR_HIP = -4,
+    UTF_ERR_OFFSETS = -5      /* batched calls: offsets are not a partition of the input */
 };
 
 /* Largest supported input: 2^40 - 1 UTF-8 bytes, 2^38 - 1 UTF-16 words. */
 #define UTF_MAX_UTF8_BYTES ((uint64_t)1 << 40)
 #define UTF_MAX_UTF16_WORDS ((uint64_t)1 << 38)
+/* Largest number of strings of one batched call. */
+#define UTF_MAX_BATCH_STRINGS ((uint64_t)1 << 31)
 
 /* ---------------------------------------------------------------------- */
 /* Validation (Section 3 rules)                                           */
@@ -154,6 +157,38 @@ int32_t convert_utf8_to_utf16le_async(const uint8_t *in, uint64_t n, uint16_t *o
                                       uint64_t out_cap, utf_result *result, void *stream);
 int32_t convert_utf16le_to_utf8_async(const uint16_t *in, uint64_t m, uint8_t *out,
                                       uint64_t out_cap, utf_result *result, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched conversion (many strings in one call)                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * UTF-8 -> UTF-16LE of k strings packed back to back in `in`: string i is
+ * in[offsets[i] .. offsets[i+1]), with offsets[0] == 0 and offsets[k] == n
+ * (k + 1 device int64 values, non-decreasing; empty strings allowed).
+ * Each string is validated and converted on its own, as by
+ * convert_utf8_to_utf16le (Section 3 rules; a string's first byte
+ * continues nothing before it and its last character must end inside it),
+ * and all of them in one pass over the buffer.
+ *
+ * Output is compact: string i's words start at out_offsets[i], the sum of
+ * utf16_length_from_utf8 of strings 0 .. i-1; out_offsets[k] is the total.
+ * `out` has room for `out_cap` words (2-byte aligned).  results[i] (device
+ * array of k) is {UTF_OK, words}, {kind, first error inside the string} or
+ * {UTF_OUTPUT_TOO_SMALL, words} when the string's words do not all fit
+ * below out_cap.  A valid string's words are exact; words in the range of
+ * an invalid string are unspecified.  If `offsets` is not a partition of
+ * the input every result is {UTF_ERR_OFFSETS, 0} and out_offsets holds 0s.
+ *
+ * Asynchronous on `stream`, like the *_async calls; every pointer except
+ * the stream is device memory.  Returns UTF_OK when enqueued, or a negative
+ * status.  Work space (a bitmap of string starts, per-string error words,
+ * per-tile and per-block offsets) is kept by the library per stream; calls
+ * on one stream are ordered, calls on different streams do not share it.
+ */
+int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const int64_t *offsets,
+                                            uint64_t k, uint16_t *out, uint64_t out_cap,
+                                            int64_t *out_offsets, utf_result *results, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Library state                                                          */

@@ -9,6 +9,8 @@ the C ABI in ``include/utfgpu.h``:
 * ``utf16_length_from_utf8(t)`` / ``utf8_length_from_utf16le(t)`` -> int
 * ``convert_utf8_to_utf16le(t, out=None)`` -> ``(status, count, out)``
 * ``convert_utf16le_to_utf8(t, out=None)`` -> ``(status, count, out)``
+* ``convert_utf8_to_utf16le_batch_async(t, offsets, out, out_offsets, results)``
+  (k strings back to back, one call)
 
 UTF-8 tensors are ``torch.uint8``; UTF-16LE tensors have 2-byte elements
 (``torch.int16`` by default: the library only reads the bytes).  All must be contiguous CUDA (HIP) tensors.  The
@@ -41,13 +43,14 @@ ERR_NULL = -1
 ERR_ALIGN = -2
 ERR_TOO_BIG = -3
 ERR_HIP = -4
+ERR_OFFSETS = -5
 
 STATUS_NAMES = {
     OK: "OK", TOO_SHORT: "TOO_SHORT", TOO_LONG: "TOO_LONG", OVERLONG: "OVERLONG",
     TOO_LARGE: "TOO_LARGE", SURROGATE: "SURROGATE", HEADER_BITS: "HEADER_BITS",
     UNPAIRED_HIGH: "UNPAIRED_HIGH", UNPAIRED_LOW: "UNPAIRED_LOW",
     OUTPUT_TOO_SMALL: "OUTPUT_TOO_SMALL", ERR_NULL: "ERR_NULL", ERR_ALIGN: "ERR_ALIGN",
-    ERR_TOO_BIG: "ERR_TOO_BIG", ERR_HIP: "ERR_HIP",
+    ERR_TOO_BIG: "ERR_TOO_BIG", ERR_HIP: "ERR_HIP", ERR_OFFSETS: "ERR_OFFSETS",
 }
 
 EXPORTS = (
@@ -55,7 +58,8 @@ EXPORTS = (
     "convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "validate_utf16le_async", "utf16_length_from_utf8_async",
     "utf8_length_from_utf16le_async", "convert_utf8_to_utf16le_async",
-    "convert_utf16le_to_utf8_async", "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
+    "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async",
+    "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
 )
 
 
@@ -78,6 +82,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "utf8_length_from_utf16le_async": ([P, U64, P, P], I32),
         "convert_utf8_to_utf16le_async": ([P, U64, P, U64, P, P], I32),
         "convert_utf16le_to_utf8_async": ([P, U64, P, U64, P, P], I32),
+        "convert_utf8_to_utf16le_batch_async": ([P, U64, P, U64, P, U64, P, P, P], I32),
         "utfgpu_release_workspace": ([], I32),
         "utfgpu_version": ([], ctypes.c_char_p),
         "utfgpu_tile_bytes": ([], U64),
@@ -246,3 +251,36 @@ def convert_utf16le_to_utf8_async(data, out, result, out_cap=None, stream=None) 
     cap = out.numel() if out_cap is None else int(out_cap)
     return int(load().convert_utf16le_to_utf8_async(_ptr(data), data.numel(), _ptr(out), cap,
                                                  result.data_ptr(), _stream(stream)))
+
+
+# batched conversion: k strings back to back
+
+def results_tensor(k: int, device="cuda") -> torch.Tensor:
+    """Device storage for ``k`` ``utf_result`` values (int64[k, 2])."""
+    return torch.zeros((max(k, 1), 2), dtype=torch.int64, device=device)
+
+
+def decode_results(t: torch.Tensor, k: int):
+    """``(status int32[k], count int64[k])`` as numpy arrays."""
+    v = t[:k].cpu()
+    status = (v[:, 0] & 0xFFFFFFFF).to(torch.int64)
+    status = torch.where(status >= 1 << 31, status - (1 << 32), status).to(torch.int32)
+    return status.numpy(), v[:, 1].numpy()
+
+
+def convert_utf8_to_utf16le_batch_async(data, offsets, out, out_offsets, results, out_cap=None,
+                                        stream=None) -> int:
+    """``offsets`` int64[k+1] (device), ``out_offsets`` int64[k+1] (device),
+    ``results`` from ``results_tensor(k)``."""
+    _dev(data, 1, "data")
+    _dev(offsets, 8, "offsets")
+    _dev(out_offsets, 8, "out_offsets")
+    _dev(out, 2, "out")
+    _dev(results, 8, "results")
+    k = offsets.numel() - 1
+    if k < 0 or out_offsets.numel() < k + 1 or results.numel() < 2 * k:
+        raise ValueError("offsets needs k+1 entries, out_offsets k+1, results k")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    return int(load().convert_utf8_to_utf16le_batch_async(
+        _ptr(data), data.numel(), offsets.data_ptr(), k, _ptr(out), cap, out_offsets.data_ptr(),
+        results.data_ptr(), _stream(stream)))

@@ -26,6 +26,10 @@ hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m,
                               u64 *result, hipStream_t stream);
 hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);
 hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);
+hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
+                             uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
+                             Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                             u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream);
 }  // namespace utfgpu
 
 using namespace utfgpu;
@@ -62,6 +66,16 @@ struct Workspace {
     u64 *status = nullptr;       // device tile status words
     u64 status_cap = 0;
     u64 launches = 0;
+    // batched calls
+    uint32_t *bad = nullptr;        // offsets check flag
+    uint32_t *starts = nullptr;     // string-start bitmap (all zero between calls)
+    u64 starts_words = 0;
+    uint16_t *blockoff = nullptr;   // per 64-byte block: output offset inside its tile
+    u64 blockoff_cap = 0;
+    u64 *tilepre = nullptr;         // per tile: output offset
+    u64 tilepre_cap = 0;
+    u64 *serr = nullptr;            // per string: first error (~0 between calls)
+    u64 serr_cap = 0;
 };
 
 std::mutex g_mu;
@@ -75,6 +89,11 @@ void free_ws(Workspace *w) {
     if (w->partials) (void)hipFree(w->partials);
     if (w->hres) (void)hipHostFree(w->hres);
     if (w->hlen) (void)hipHostFree(w->hlen);
+    if (w->bad) (void)hipFree(w->bad);
+    if (w->starts) (void)hipFree(w->starts);
+    if (w->blockoff) (void)hipFree(w->blockoff);
+    if (w->tilepre) (void)hipFree(w->tilepre);
+    if (w->serr) (void)hipFree(w->serr);
     delete w;
 }
 
@@ -135,6 +154,38 @@ hipError_t get_ws(hipStream_t s, u64 ntiles, Workspace **out) {
         w->launches++;
     }
     *out = w;
+    return hipSuccess;
+}
+
+// Grow a device array to at least `need` elements (new memory filled with
+// byte `fill`); the stream is drained first, since queued work may still
+// use the old array.
+template <class T>
+hipError_t grow(T **p, u64 *cap, u64 need, int fill, hipStream_t s) {
+    if (need <= *cap) return hipSuccess;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const u64 c = need + need / 4 + 64;
+    if ((e = hipMalloc(p, c * sizeof(T))) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(*p, fill, c * sizeof(T), s)) != hipSuccess) return e;
+    *cap = c;
+    return hipSuccess;
+}
+
+// Batched-call arrays for `ntiles` tiles and `k` strings.
+hipError_t get_batch(Workspace *w, u64 ntiles, u64 k, hipStream_t s) {
+    hipError_t e;
+    if (!w->bad) {
+        if ((e = hipMalloc(&w->bad, sizeof(uint32_t))) != hipSuccess) return e;
+    }
+    const u64 positions = ntiles * (u64)kTileBytes + 128;   // every tile and the chunk past the last
+    if ((e = grow(&w->starts, &w->starts_words, positions / 32 + 2, 0, s)) != hipSuccess) return e;
+    if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 64 + 2, 0, s)) != hipSuccess) return e;
+    if ((e = grow(&w->tilepre, &w->tilepre_cap, ntiles + 1, 0, s)) != hipSuccess) return e;
+    if ((e = grow(&w->serr, &w->serr_cap, k + 1, 0xFF, s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -372,6 +423,29 @@ int32_t utfgpu_release_workspace(void) {
     }
     g_ws.clear();
     return rc;
+}
+
+int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const int64_t *offsets, uint64_t k,
+                                            uint16_t *out, uint64_t out_cap, int64_t *out_offsets,
+                                            utf_result *results, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return c;
+    if (!offsets || !out_offsets || (k > 0 && !results)) return UTF_ERR_NULL;
+    if (!out && out_cap > 0) return UTF_ERR_NULL;
+    if (reinterpret_cast<uintptr_t>(out) & 1u) return UTF_ERR_ALIGN;
+    if (k >= UTF_MAX_BATCH_STRINGS) return UTF_ERR_TOO_BIG;
+    hipStream_t s = as_stream(stream);
+    if (k == 0) return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    const long long head = n > 0 ? head_bytes(in) : 0;
+    const u64 nt = n > 0 ? utf8_tiles_for(head, (long long)n) : 0;
+    Workspace *w;
+    if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
+    if (get_batch(w, nt, k, s) != hipSuccess) return UTF_ERR_HIP;
+    if (launch_utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
+                          reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
+                          w->blockoff, w->tilepre, w->serr, w->bad, s) != hipSuccess)
+        return UTF_ERR_HIP;
+    return UTF_OK;
 }
 
 const char *utfgpu_version(void) { return "utfgpu 0.1 gfx950"; }

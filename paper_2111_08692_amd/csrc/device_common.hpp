@@ -58,6 +58,7 @@ enum : uint32_t {
     kUnpairedLow = 8,
     kOutputTooSmall = 9,
 };
+constexpr int32_t kErrOffsets = -5;   // batched calls: the offsets array is not a valid partition
 
 typedef uint64_t u64;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

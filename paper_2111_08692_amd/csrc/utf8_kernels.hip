@@ -39,6 +39,19 @@ enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kQuad = 3, kAny = 4 };
 // Classes whose waves can hold four-byte characters (two slots each).
 constexpr bool has4(uint32_t cls) { return cls >= kQuad; }
 
+// Batched calls: k strings, string i occupying input bytes [offsets[i],
+// offsets[i+1]).  Outputs are compact: string i's words start at the sum of
+// the length-query values of strings 0..i-1, which is the scan of the
+// per-byte widths at offsets[i], so one device-wide scan serves them all.
+struct BatchCtx {
+    const int64_t *offsets;   // k + 1 boundaries
+    u64 k;
+    const uint16_t *starts;   // bitmap over frame positions: a non-empty string starts here
+    uint16_t *blockoff;       // per 64-byte block of the frame: its output offset inside its tile
+    u64 *tilepre;             // per tile: output offset of the tile
+    u64 *serr;                // per string: min (position << 4 | kind), ~0 when valid
+};
+
 // Slots one wave stages at a time (kGroup rows).  Valid input needs at most
 // one slot per byte of the group plus one: a group can end with the leading
 // byte of a four-byte character (two slots) whose continuation bytes lie
@@ -167,8 +180,35 @@ struct Survey {
     uint32_t width[kRows];
 };
 
+// Batched calls: string starts as bit 7 of each byte of a dword, from four
+// bitmap bits (bit j for byte j).
+__device__ __forceinline__ uint32_t spread4(uint32_t b) { return ((b & 15u) * 0x10204080u) & 0x80808080u; }
+
+// Bitmap bits of string starts for the lane's chunk of each row: bits
+// 16..31 for the chunk's positions, bits 0..15 for the 16 positions before.
+struct StartBits {
+    uint32_t b[kRows];
+};
+
+// The start bits of each row's chunk and the 16 positions before it.  The
+// bitmap covers every tile of the call and 64 positions past them.
+__device__ __forceinline__ void load_start_bits(const BatchCtx &bc, long long wbase, uint32_t lane, StartBits &sb) {
+    const long long c0 = (wbase >> 4) + lane;   // chunk index of row 0
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const long long ci = c0 + r * (kRowBytes / 16);
+        const uint32_t cur = bc.starts[ci];
+        const uint32_t before = ci >= 1 ? (uint32_t)bc.starts[ci - 1] : 0u;
+        sb.b[r] = (cur << 16) | before;
+    }
+}
+
+// With kBatch, a string start acts as a buffer end for the detector: a
+// leading byte before it announces nothing past it (such an announcement
+// is flagged), and a continuation byte at it is covered by nothing.
+template <bool kBatch>
 __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase, long long head, long long end,
-                                            uint32_t lane, Survey &sv) {
+                                            uint32_t lane, Survey &sv, const StartBits &sb) {
     uint32_t a80 = lane == 0 ? (t.hp & 0xFFFFFF00u) : 0u;
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
@@ -197,6 +237,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = prev_dword(t, r, lane);
         uint32_t pc0 = ge_c0(p), pe0 = ge_e0(p), pf0 = ge_f0(p);
+        uint32_t ps = kBatch ? spread4(sb.b[r] >> 12) : 0u;   // starts among the 4 positions before
         uint32_t w = 16;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -204,10 +245,21 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
             const uint32_t c0 = ge_c0(x);
             const uint32_t e0 = c0 & (x << 2);
             const uint32_t f0 = e0 & (x << 3);
-            const uint32_t must = __builtin_amdgcn_alignbyte(c0, pc0, 3) | __builtin_amdgcn_alignbyte(e0, pe0, 2) |
-                                  __builtin_amdgcn_alignbyte(f0, pf0, 1);
+            const uint32_t m1 = __builtin_amdgcn_alignbyte(c0, pc0, 3), m2 = __builtin_amdgcn_alignbyte(e0, pe0, 2),
+                           m3 = __builtin_amdgcn_alignbyte(f0, pf0, 1);
             const uint32_t cb = lane_cont_bits(t, r, k, wbase, head, end, lane);
-            mis |= (must & 0x80808080u) ^ cont_bits(x);
+            if (kBatch) {
+                const uint32_t s0 = spread4(sb.b[r] >> (16 + 4 * k));     // start at t
+                const uint32_t s1 = __builtin_amdgcn_alignbyte(s0, ps, 3);  // start at t-1
+                const uint32_t s2 = __builtin_amdgcn_alignbyte(s0, ps, 2);  // start at t-2
+                const uint32_t x01 = s0 | s1, x012 = x01 | s2;
+                const uint32_t mi = (m1 & ~s0) | (m2 & ~x01) | (m3 & ~x012);   // announced within the string
+                const uint32_t mc = (m1 & s0) | (m2 & x01) | (m3 & x012);      // announced past its end
+                mis |= ((mi & 0x80808080u) ^ cont_bits(x)) | (mc & 0x80808080u);
+                ps = s0;
+            } else {
+                mis |= ((m1 | m2 | m3) & 0x80808080u) ^ cont_bits(x);
+            }
             aE0 |= e0;
             aF0 |= f0;
             aMid |= c0 & ~f0;
@@ -277,7 +329,11 @@ __device__ __noinline__ u64 tile_width16(const uint8_t *frame, long long head, l
 // The window of a four-byte character's low surrogate is stored with its
 // first byte xor 0x70, which maps F0..FF into the continuation range 80..8F
 // -- a value no leading byte's window starts with.
-template <uint32_t kClass>
+//
+// kFull (batched calls): an invalid string can end in the lane's first
+// dword and a valid one start later in the chunk, so the first leading
+// byte is looked for in the whole chunk.
+template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t gof, uint32_t *wst, long long wbase,
                                             long long head, long long end, uint32_t lane) {
     uint8_t *sb = (uint8_t *)wst;
@@ -307,7 +363,7 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
     // rewrite the first slot
     uint32_t win = 0;
     bool has = false;
-    if (!t.edge) {
+    if (!kFull && !t.edge) {
         has = lead0 != 0;
         const uint32_t p = (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3;   // first leading byte
         win = __builtin_amdgcn_alignbyte(t.d[r][1], t.d[r][0], p);
@@ -519,7 +575,9 @@ __device__ __forceinline__ uint32_t overlong2_bits(uint32_t x) {
 }
 
 // Stage the lane's chunk of row r: words at halfword o + slot.  Returns
-// whether a value rule failed (C0 or C1 leading byte).
+// whether a value rule failed (C0 or C1 leading byte).  kFull as for
+// scatter_row.
+template <bool kFull>
 __device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
                                                long long head, long long end, uint32_t lane) {
     uint16_t *st16 = (uint16_t *)wst;
@@ -548,7 +606,7 @@ __device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32
     // rewrite the first slot (see scatter_row)
     uint32_t v = 0;
     bool has;
-    if (!t.edge) {
+    if (!kFull && !t.edge) {
         has = lead0 != 0;
         v = word_at2(ce0, co0, (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3);
     } else {
@@ -572,10 +630,51 @@ __device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32
     return bad != 0;
 }
 
+// Words of a wave's leading bytes stored one by one at their slots (`slot`:
+// the output word of the lane's chunk of each row), from bytes reloaded
+// from memory: the fallback for groups whose slots do not fit the stage,
+// which only invalid input produces.  A valid character gets its exact
+// words; an invalid one gets some words of its own width.
+__device__ __noinline__ void direct_words(const uint8_t *frame, long long head, long long end, long long wbase,
+                                          uint32_t lane, u64 s0, u64 s1, u64 s2, u64 s3, uint16_t *out,
+                                          u64 out_cap) {
+    for (int r = 0; r < kRows; ++r) {
+        const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
+        u64 o = r == 0 ? s0 : (r == 1 ? s1 : (r == 2 ? s2 : s3));
+        uint32_t b[19];
+        for (int i = 0; i < 19; ++i) {
+            const long long q = q0 + i;
+            b[i] = (q >= head && q < end) ? frame[q] : 0u;
+        }
+        for (int i = 0; i < 16; ++i) {
+            const long long q = q0 + i;
+            const uint32_t b0 = b[i], b1 = b[i + 1] & 0x3Fu, b2 = b[i + 2] & 0x3Fu, b3 = b[i + 3] & 0x3Fu;
+            if (q < head || q >= end || is_cont(b0)) continue;
+            uint32_t w0, w1 = 0;
+            bool two = false;
+            if (b0 < 0x80u) {
+                w0 = b0;
+            } else if (b0 < 0xE0u) {
+                w0 = ((b0 & 0x1Fu) << 6) | b1;
+            } else if (b0 < 0xF0u) {
+                w0 = ((b0 & 0x0Fu) << 12) | (b1 << 6) | b2;
+            } else {
+                const uint32_t cp = ((b0 & 0x07u) << 18) | (b1 << 12) | (b2 << 6) | b3;
+                w0 = 0xD7C0u + (cp >> 10);
+                w1 = 0xDC00u | (cp & 0x3FFu);
+                two = true;
+            }
+            if (o < out_cap) out[o] = (uint16_t)w0;
+            if (two && o + 1 < out_cap) out[o + 1] = (uint16_t)w1;
+            o += two ? 2 : 1;
+        }
+    }
+}
+
 // The wave's conversion after the tile prefix is known.  `staged0`: group
 // 0 has been staged already.  Returns whether a value rule failed.  Rows
 // are written with their unfinished last block carried to the next row.
-template <uint32_t kClass>
+template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
                                              const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
                                              u64 out_cap, uint32_t *wst, long long wbase, long long head,
@@ -600,12 +699,12 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
         if (kClass == kUpTo2) {   // words straight from the bytes
 #pragma unroll
             for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
-                bad |= scatter_words2(t, r, h + gof[r], wst, wbase, head, end, lane);
+                bad |= scatter_words2<kFull>(t, r, h + gof[r], wst, wbase, head, end, lane);
         } else {
             if (g > 0 || !staged0)
 #pragma unroll
                 for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
-                    scatter_row<kClass>(t, r, gof[r], wst, wbase, head, end, lane);
+                    scatter_row<kClass, kFull>(t, r, gof[r], wst, wbase, head, end, lane);
             wave_lds_sync();
             bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
         }
@@ -690,6 +789,80 @@ __device__ __noinline__ u64 exact_chunk(uint32_t v0, uint32_t v1, uint32_t v2, u
     return ((u64)(q0 + (long long)first - 4 - head) << 4) | kind;
 }
 
+// The string that owns input byte p: the largest i with offsets[i] <= p
+// (an empty string owns no byte, and is never the largest such i).
+__device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 k, long long p) {
+    u64 lo = 0, hi = k;
+    while (hi - lo > 1) {
+        const u64 mid = (lo + hi) / 2;
+        if (offsets[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Batched form of exact_chunk: string starts act as buffer ends (a byte at
+// a start continues nothing before it), `sbits` bit i marks a start at
+// chunk position i - 16.  Each string's first flagged byte in the chunk is
+// reported to that string's error word.
+__device__ __forceinline__ void exact_chunk_batch(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3, uint32_t v4,
+                                               uint32_t v5, u64 sbits, long long q0, long long head, bool halo,
+                                               BatchCtx bc) {
+    const uint32_t v[6] = {v0, v1, v2, v3, v4, v5};
+    uint32_t badm[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {   // dword i holds chunk positions 4i-4 .. 4i-1
+        const uint32_t x = v[i], xn = v[i + 1], xp = i > 0 ? v[i - 1] : 0u;
+        const uint32_t sp = spread4((uint32_t)(sbits >> (8 + 4 * i)));    // starts in the dword before
+        const uint32_t st = spread4((uint32_t)(sbits >> (12 + 4 * i)));   // starts in this dword
+        const uint32_t sn = spread4((uint32_t)(sbits >> (16 + 4 * i)));   // starts in the dword after
+        const uint32_t c0 = ge_c0(x), e0 = ge_e0(x), f0 = ge_f0(x);
+        // continuation bytes that continue this string (none at a start)
+        const uint32_t k1 = cont_bits(__builtin_amdgcn_alignbyte(xn, x, 1)) & ~__builtin_amdgcn_alignbyte(sn, st, 1);
+        const uint32_t k2 = cont_bits(__builtin_amdgcn_alignbyte(xn, x, 2)) & ~__builtin_amdgcn_alignbyte(sn, st, 2);
+        const uint32_t k3 = cont_bits(__builtin_amdgcn_alignbyte(xn, x, 3)) & ~__builtin_amdgcn_alignbyte(sn, st, 3);
+        const uint32_t shortb = (c0 & ~k1) | (e0 & ~k2) | (f0 & ~k3);
+        const uint32_t lead_bad = (shortb | value_bits<kAny>(x, __builtin_amdgcn_alignbyte(xn, x, 1))) & 0x80808080u;
+        if (i == 0) {
+            badm[i] = halo ? lead_bad & 0x80808000u : 0u;
+        } else {
+            const uint32_t m1 = __builtin_amdgcn_alignbyte(c0, ge_c0(xp), 3),
+                           m2 = __builtin_amdgcn_alignbyte(e0, ge_e0(xp), 2),
+                           m3 = __builtin_amdgcn_alignbyte(f0, ge_f0(xp), 1);
+            const uint32_t s1 = __builtin_amdgcn_alignbyte(st, sp, 3), s2 = __builtin_amdgcn_alignbyte(st, sp, 2);
+            const uint32_t mi = (m1 & ~st) | (m2 & ~(st | s1)) | (m3 & ~(st | s1 | s2));
+            badm[i] = lead_bad | (cont_bits(x) & ~mi & 0x80808080u);
+        }
+    }
+    int lastpos = -100;   // position of the last report (its string's first flag here)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        uint32_t m = badm[i];
+        while (m) {
+            const uint32_t byte = (uint32_t)__builtin_ctz(m) >> 3;
+            m &= m - 1;
+            const int pos = 4 * i - 4 + (int)byte;          // chunk position
+            // no string starts in (lastpos, pos]: same string, already reported
+            if (lastpos > -100 && ((sbits >> (17 + lastpos)) & ((1ull << (pos - lastpos)) - 1ull)) == 0) continue;
+            lastpos = pos;
+            const long long pin = q0 + pos - head;          // input position
+            const u64 idx = owner_string(bc.offsets, bc.k, pin);
+            // the byte and the three after it, bytes of the next string read as zero
+            const uint32_t lo = i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : (i == 3 ? v3 : v4)));
+            const uint32_t hi = i == 0 ? v1 : (i == 1 ? v2 : (i == 2 ? v3 : (i == 3 ? v4 : v5)));
+            uint32_t w = __builtin_amdgcn_alignbyte(hi, lo, byte);
+            const uint32_t sw = (uint32_t)(sbits >> (16 + pos)) & 15u;   // starts at pos .. pos+3
+            if (sw & 2u) w &= 0x000000FFu;
+            else if (sw & 4u) w &= 0x0000FFFFu;
+            else if (sw & 8u) w &= 0x00FFFFFFu;
+            const uint32_t b0 = w & 0xFFu;
+            const uint32_t kind = is_cont(b0) ? (uint32_t)kTooLong
+                                              : lead_kind(b0, (w >> 8) & 0xFFu, (w >> 16) & 0xFFu, w >> 24);
+            min_agent(bc.serr + idx, ((u64)(pin - bc.offsets[idx]) << 4) | kind);
+        }
+    }
+}
+
 template <uint32_t kClass>
 __device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) {
     uint32_t bad = 0;
@@ -709,11 +882,10 @@ __device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) 
 // ------------------------------------------------------------------------
 // Validation and conversion: tile t = workgroup t.
 // ------------------------------------------------------------------------
-template <bool kConvert>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf8_tile_kernel(const uint8_t *__restrict__ frame, long long head,
-                                                            long long n, uint16_t *__restrict__ out, u64 out_cap,
-                                                            u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
-                                                            u64 ntiles, int spin_limit) {
+template <bool kConvert, bool kBatch>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf8_tile_kernel(
+    const uint8_t *__restrict__ frame, long long head, long long n, uint16_t *__restrict__ out, u64 out_cap,
+    u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
     __shared__ u64 s_prefix;
@@ -727,17 +899,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     LaneBytes t;
     issue_span(frame, end, wbase, lane, t);
     const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
+    // batched calls: string starts of each row's chunk and of the 16
+    // positions before it (the bitmap covers the whole frame and 64 past)
+    StartBits sb;
+    if (kBatch) load_start_bits(bc, wbase, lane, sb);
     finish_span(head, end, wbase, lane, t);
     {
         Survey sv;
-        survey_span(t, wbase, head, end, lane, sv);
+        survey_span<kBatch>(t, wbase, head, end, lane, sv, sb);
         // the all-ASCII shortcut widens whole chunks: not for waves at the ends
         const uint32_t cls = (sv.cls == kAscii && t.edge) ? kUpTo2 : sv.cls;
         bool flag = sv.mis;
         fence_values(t);
         // a wave whose detector fired, when an error before it is already
         // known: its output lies past the valid prefix and is not written
-        const bool moot = kConvert && __ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
+        const bool moot =
+            !kBatch && kConvert && __ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
 
         if (kConvert) {
             // in-wave offsets (row-major) and wave total
@@ -771,39 +948,60 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 if (lane == 0) {
                     s_prefix = prefix;
                     if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
+                    if (kBatch) bc.tilepre[tile] = prefix;
                 }
             }
+            if (kBatch && (lane & 3u) == 0) {   // in-tile output offset of every 64-byte block
+                const long long blk = ((wbase >> 4) + lane) >> 2;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r)
+                    bc.blockoff[blk + r * (kRowBytes / 64)] = (uint16_t)(wave_off + rowbase[r] + gof[r]);
+            }
             uint32_t *wst = stage + wave * kStageWords;
-            if (!moot) switch (cls) {   // the first group needs no prefix
+            // batched calls: a group of an invalid string can announce more
+            // slots than the stage holds; the strings after it in the wave
+            // still need their words, stored one by one instead
+            bool direct = false;
+            if (kBatch && has4(cls))
+#pragma unroll
+                for (int g = 0; g < kRows / kGroup; ++g)
+                    direct |= rowbase[(g + 1) * kGroup] - rowbase[g * kGroup] > kStageSlots;
+            if (!moot && !direct) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
-                case kUpTo3: scatter_row<kUpTo3>(t, 0, gof[0], wst, wbase, head, end, lane); break;
-                case kQuad: scatter_row<kQuad>(t, 0, gof[0], wst, wbase, head, end, lane); break;
-                default: scatter_row<kAny>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                case kUpTo3: scatter_row<kUpTo3, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                case kQuad: scatter_row<kQuad, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                default: scatter_row<kAny, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
             }
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
-            if (!moot) switch (cls) {
+            if (direct) {
+                u64 slot[kRows];
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) slot[r] = base + rowbase[(r / kGroup) * kGroup] + gof[r];
+                direct_words(frame, head, end, wbase, lane, slot[0], slot[1], slot[2], slot[3], out, out_cap);
+                flag = true;
+            } else if (!moot) switch (cls) {
                 case kAscii:
                     if (base + kWaveBytes <= out_cap)
                         widen_store_wave(t, out, base, lane);
                     else
-                        convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                        convert_wave<kUpTo2, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                              false);
                     break;
                 case kUpTo2:
-                    flag |= convert_wave<kUpTo2>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                    flag |= convert_wave<kUpTo2, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                                  true);
                     break;
                 case kUpTo3:
-                    flag |= convert_wave<kUpTo3>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                    flag |= convert_wave<kUpTo3, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                                  true);
                     break;
                 case kQuad:
-                    flag |= convert_wave<kQuad>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                    flag |= convert_wave<kQuad, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                                 true);
                     break;
                 default:
-                    flag |= convert_wave<kAny>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
+                    flag |= convert_wave<kAny, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
                                                true);
                     break;
             }
@@ -819,7 +1017,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // exact first error over this lane's positions (and, for the first
         // lane, the leading bytes among the three positions before the wave),
         // unless an error before the wave is already known
-        if (__ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - 3 - head) {
+        if (kBatch && __ballot(flag)) {   // per string
+            const long long c0 = (wbase >> 4) + lane;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                const long long q0 = wbase + r * kRowBytes + 16 * (long long)lane;
+                const uint32_t p = prev_dword(t, r, lane), nx = next_dword(t, r, lane);
+                const long long ci = c0 + r * (kRowBytes / 16);
+                const u64 bits = (u64)bc.starts[ci - 1 >= 0 ? ci - 1 : 0] * (ci >= 1) |
+                                 ((u64)bc.starts[ci] << 16) | ((u64)bc.starts[ci + 1] << 32);
+                exact_chunk_batch(p, t.d[r][0], t.d[r][1], t.d[r][2], t.d[r][3], nx, bits, q0, head,
+                                  r == 0 && lane == 0, bc);
+            }
+        }
+        if (!kBatch && __ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - 3 - head) {
             u64 err = ~0ull;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
@@ -927,16 +1138,122 @@ u64 utf8_tiles_for(long long head, long long n) {
 hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
     const u64 ntiles = utf8_tiles_for(head, n);
+    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     if (convert)
-        hipLaunchKernelGGL(utf8_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head, n,
-                           out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+        hipLaunchKernelGGL((utf8_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     else
-        hipLaunchKernelGGL(utf8_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head,
-                           n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+        hipLaunchKernelGGL((utf8_tile_kernel<false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(ctrl, result, nullptr, convert ? kFinConvert : kFinValidate, (u64)n, out_cap, nullptr,
                            0, stream);
+}
+
+// ------------------------------------------------------------------------
+// Batched UTF-8 -> UTF-16LE
+// ------------------------------------------------------------------------
+// Marks the first byte of every non-empty string in the start bitmap and
+// checks the offsets (0 = offsets[0] <= ... <= offsets[k] = n); a bad array
+// sets `bad` and marks nothing for the strings it concerns.
+__global__ void batch_prep_kernel(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
+                                  uint32_t *bad) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > k) return;
+    const int64_t a = offsets[i];
+    if (i == 0 && a != 0) atomicOr(bad, 1u);
+    if (i == k) {
+        if (a != n) atomicOr(bad, 1u);
+        return;
+    }
+    const int64_t b = offsets[i + 1];
+    if (a < 0 || b < a || b > n) {
+        atomicOr(bad, 1u);
+        return;
+    }
+    if (b > a) {
+        const u64 q = (u64)(head + a);
+        atomicOr(starts + (q >> 5), 1u << (q & 31u));
+    }
+}
+
+// Output offset of input byte p: the tile's offset, the offset of p's
+// 64-byte block inside the tile, and the widths of the block's bytes
+// before p.
+__device__ u64 batch_out_offset(const uint8_t *frame, long long head, long long n, const BatchCtx &bc, u64 total,
+                                int64_t p) {
+    if (p >= n) return total;
+    const long long q = head + p;
+    const long long b0 = q & ~63ll;
+    u64 w = bc.tilepre[q / kTileBytes] + bc.blockoff[q >> 6];
+    for (long long c = b0; c < q; c += 16) {
+        const long long e = c + 16 < q ? c + 16 : q;
+        w += load_chunk_width16(frame, head, e, c);
+    }
+    return w;
+}
+
+// Per string: output offsets, result, and the reset of its error word and
+// start bit for the next call.
+__global__ void batch_post_kernel(const uint8_t *frame, long long head, long long n, BatchCtx bc, Ctrl *ctrl,
+                                  int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
+                                  uint32_t *starts) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > bc.k) return;
+    const bool ok = *bad == 0;
+    const u64 total = ld_agent(&ctrl->total);
+    const int64_t a = bc.offsets[i];
+    const u64 oa = ok ? batch_out_offset(frame, head, n, bc, total, a) : 0;
+    out_offsets[i] = (int64_t)oa;
+    if (i == bc.k) return;
+    const int64_t b = bc.offsets[i + 1];
+    // the start bit batch_prep_kernel set for this string (same test)
+    if (a >= 0 && b > a && b <= n) {
+        const u64 q = (u64)(head + a);
+        atomicAnd(starts + (q >> 5), ~(1u << (q & 31u)));
+    }
+    const u64 e = bc.serr[i];
+    bc.serr[i] = ~0ull;
+    results[i].pad = 0;
+    if (!ok) {
+        results[i].status = kErrOffsets;
+        results[i].count = 0;
+        return;
+    }
+    const u64 ob = batch_out_offset(frame, head, n, bc, total, b);
+    if (e != ~0ull) {
+        results[i].status = (int32_t)(e & 15u);
+        results[i].count = e >> 4;
+    } else {
+        results[i].status = ob > out_cap ? (int32_t)kOutputTooSmall : (int32_t)kOk;
+        results[i].count = ob - oa;
+    }
+}
+
+__global__ void clear_u32_kernel(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
+                             uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
+                             Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                             u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream) {
+    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, bad);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const u64 ntiles = utf8_tiles_for(head, n);
+    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr};
+    if (n > 0)
+        hipLaunchKernelGGL((utf8_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
+    hipLaunchKernelGGL(batch_post_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, n, bc, ctrl, out_offsets,
+                       results, out_cap, (const uint32_t *)bad, starts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // reset the control block (error word unused here, total, epoch)
+    return launch_finalize(ctrl, scratch_result, nullptr, kFinConvert, (u64)n, out_cap, nullptr, 0, stream);
 }
 
 int partial_blocks(long long units, long long units_per_block) {
