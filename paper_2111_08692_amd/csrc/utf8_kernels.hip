@@ -375,10 +375,13 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
             if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
         }
         has = p < 16;
-        const uint32_t j = p >> 2;
-        const uint32_t lo = j == 0 ? t.d[r][0] : (j == 1 ? t.d[r][1] : (j == 2 ? t.d[r][2] : t.d[r][3]));
-        const uint32_t hi = j == 0 ? t.d[r][1] : (j == 1 ? t.d[r][2] : (j == 2 ? t.d[r][3] : nx_row));
-        win = __builtin_amdgcn_alignbyte(hi, lo, p & 3u);
+        // select among computed windows, never among the bytes by index
+        // (that would keep the bytes in memory instead of registers)
+        const uint32_t j = p >> 2, sh = p & 3u;
+        const uint32_t a0 = t.d[r][0], a1 = t.d[r][1], a2 = t.d[r][2], a3 = t.d[r][3];
+        const uint32_t w0 = __builtin_amdgcn_alignbyte(a1, a0, sh), w1 = __builtin_amdgcn_alignbyte(a2, a1, sh),
+                       w2 = __builtin_amdgcn_alignbyte(a3, a2, sh), w3 = __builtin_amdgcn_alignbyte(nx_row, a3, sh);
+        win = j == 0 ? w0 : (j == 1 ? w1 : (j == 2 ? w2 : w3));
     }
     if (has) {
         const uint32_t a = has4(kClass) ? min(4u * gof, kLast) : 4u * gof;
@@ -564,6 +567,28 @@ __device__ __forceinline__ void words2(uint32_t x, uint32_t nx, uint32_t &ce, ui
     co = (mo & ((po << 6) | qo)) | (~mo & po);
 }
 
+// ------------------------------------------------------------------------
+// Validation only: value rules on every leading byte, from its byte and
+// the next (SWAR over the dword x, with y = the bytes one position later).
+// ------------------------------------------------------------------------
+template <uint32_t kClass>
+__device__ __forceinline__ uint32_t value_bits(uint32_t x, uint32_t y) {
+    uint32_t bad = 0;
+    if (kClass != kQuad) {   // kQuad waves hold no leading bytes C0..EF
+        bad = zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);                  // C0, C1
+        if (kClass == kUpTo2) return bad;
+        const uint32_t y5 = y << 2;                                          // bit 5 of the next byte
+        bad |= zero_bytes(x ^ 0xE0E0E0E0u) & ~y5;                            // E0 80..9F: overlong
+        bad |= zero_bytes(x ^ 0xEDEDEDEDu) & y5;                             // ED A0..BF: surrogate
+        if (kClass == kUpTo3) return bad;
+    }
+    const uint32_t y54 = (y << 2) | (y << 3);                                // bit 5 or 4 of the next byte
+    bad |= zero_bytes(x ^ 0xF0F0F0F0u) & ~y54;                               // F0 80..8F: overlong
+    bad |= zero_bytes(x ^ 0xF4F4F4F4u) & y54;                                // F4 90..BF: too large
+    bad |= ((x & 0x7F7F7F7Fu) + 0x0B0B0B0Bu) & x;                            // F5..FF
+    return bad & 0x80808080u;
+}
+
 // Word at position k (0..3) of a dword from its packed halves.
 __device__ __forceinline__ uint32_t word_at2(uint32_t ce, uint32_t co, uint32_t k) {
     return ((k & 1u) ? co : ce) >> (16 * (k >> 1));
@@ -574,11 +599,114 @@ __device__ __forceinline__ uint32_t overlong2_bits(uint32_t x) {
     return zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);
 }
 
+// ------------------------------------------------------------------------
+// Waves of ASCII and four-byte characters: words computed at every position
+// ------------------------------------------------------------------------
+// A four-byte character (leading byte A, continuation bytes B, C, D) becomes
+// the high surrogate D7C0 + ((A & 07) << 8) + ((B & 3F) << 2) + ((C & 3F) >> 4)
+// and the low surrogate DC00 + ((C & 0F) << 6) + (D & 3F).  In 16-bit
+// arithmetic, whose wrap-around drops the marker bits of A, B and D:
+//   high = A*256 + B*4 + (C >> 4) + E5B8,   low = (C & 0F)*64 + D + DB80.
+// Two positions per register in 16-bit halves, as for the 2-byte class.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_h2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+template <uint32_t kSel, uint32_t kMaskSel>
+__device__ __forceinline__ void words4_half(uint32_t x, uint32_t y, uint32_t z, uint32_t w, uint32_t mf,
+                                            uint32_t &hw, uint32_t &lw) {
+    const uint32_t a = __builtin_amdgcn_perm(0u, x, kSel), b = __builtin_amdgcn_perm(0u, y, kSel),
+                   c = __builtin_amdgcn_perm(0u, z, kSel), d = __builtin_amdgcn_perm(0u, w, kSel);
+    const uint32_t hi = as_u32(as_h2(a) * (unsigned short)256 + as_h2(b) * (unsigned short)4 +
+                               (as_h2(c) >> (unsigned short)4) + (unsigned short)0xE5B8);
+    lw = as_u32(as_h2(c & 0x000F000Fu) * (unsigned short)64 + as_h2(d) + (unsigned short)0xDB80);
+    const uint32_t m = __builtin_amdgcn_perm(0u, mf, kMaskSel);
+    hw = (m & hi) | (~m & a);   // the byte itself at the other positions
+}
+
+// First words (he even positions, ho odd) and low surrogates (le, lo) of
+// the four positions of dword x (next dword nx).
+__device__ __forceinline__ void words4(uint32_t x, uint32_t nx, uint32_t &he, uint32_t &ho, uint32_t &le,
+                                       uint32_t &lo) {
+    const uint32_t y = __builtin_amdgcn_alignbyte(nx, x, 1), z = __builtin_amdgcn_alignbyte(nx, x, 2),
+                   w = __builtin_amdgcn_alignbyte(nx, x, 3);
+    const uint32_t f0 = ge_f0(x) & 0x80808080u;
+    const uint32_t mf = (f0 << 1) - (f0 >> 7);   // 0xFF for the bytes >= F0
+    words4_half<0x0c020c00u, 0x02020000u>(x, y, z, w, mf, he, le);
+    words4_half<0x0c030c01u, 0x03030101u>(x, y, z, w, mf, ho, lo);
+}
+
+// Bits 0..3 from bit 7 of bytes 0..3.
+__device__ __forceinline__ uint32_t nibble_of(uint32_t m) {
+    m >>= 7;
+    return (m | (m >> 7) | (m >> 14) | (m >> 21)) & 15u;
+}
+
+// Stage the lane's chunk of row r (a wave away from the input's ends):
+// every position stores its first word at halfword o + slot and its low
+// surrogate one halfword further, in position order.  The last positions
+// of a lane may leave stray words in the next lane's first two slots; each
+// lane rewrites its own first two slots at the end: the first character's
+// first word, then its low surrogate or the second character's word.
+// Returns whether a value rule failed.
+__device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, uint32_t lane) {
+    uint16_t *st16 = (uint16_t *)wst;
+    const uint32_t nx_row = next_dword(t, r, lane);
+    const uint32_t o0 = o;
+    uint32_t bad = 0, h0e = 0, h0o = 0, l0e = 0, l0o = 0, h1e = 0, h1o = 0, L = 0, F = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t x = t.d[r][j];
+        const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
+        const uint32_t lead = ~cont_bits(x) & 0x80808080u;
+        const uint32_t f0 = ge_f0(x) & 0x80808080u;
+        uint32_t he, ho, le, lo;
+        words4(x, nx, he, ho, le, lo);
+        bad |= value_bits<kQuad>(x, __builtin_amdgcn_alignbyte(nx, x, 1));
+        if (j == 0) {
+            h0e = he; h0o = ho; l0e = le; l0o = lo;
+            L = nibble_of(lead);
+            F = nibble_of(f0);
+        } else if (j == 1) {
+            h1e = he; h1o = ho;
+            L |= nibble_of(lead) << 4;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            st16[o] = (uint16_t)word_at2(he, ho, (uint32_t)k);
+            st16[o + 1] = (uint16_t)word_at2(le, lo, (uint32_t)k);
+            o += __builtin_amdgcn_ubfe(lead, 8 * k + 7, 1) + __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1);
+        }
+    }
+    // a first dword without a leading byte is invalid input: every slot of
+    // the lane then lies past the valid prefix
+    if (L & 15u) {
+        const uint32_t p1 = (uint32_t)__builtin_ctz(L);
+        st16[o0] = (uint16_t)word_at2(h0e, h0o, p1);
+        const uint32_t rest = L & (L - 1u);
+        if ((F >> p1) & 1u) {
+            st16[o0 + 1] = (uint16_t)word_at2(l0e, l0o, p1);
+        } else if (rest) {   // valid input has its second leading byte right after a one-byte first
+            const uint32_t p2 = (uint32_t)__builtin_ctz(rest);
+            st16[o0 + 1] = (uint16_t)(p2 < 4 ? word_at2(h0e, h0o, p2) : word_at2(h1e, h1o, p2 - 4));
+        }
+    }
+    return bad != 0;
+}
+
+// Words of the dword x (next dword nx) for a wave of class kClass, and
+// the value rules of its leading bytes.
+template <uint32_t kClass>
+__device__ __forceinline__ uint32_t class_words(uint32_t x, uint32_t nx, uint32_t &ce, uint32_t &co) {
+    static_assert(kClass == kUpTo2, "words computed in registers: 1- and 2-byte classes");
+    words2(x, nx, ce, co);
+    return overlong2_bits(x);
+}
+
 // Stage the lane's chunk of row r: words at halfword o + slot.  Returns
-// whether a value rule failed (C0 or C1 leading byte).  kFull as for
-// scatter_row.
-template <bool kFull>
-__device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
+// whether a value rule failed.  kFull as for scatter_row.
+template <uint32_t kClass, bool kFull>
+__device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
                                                long long head, long long end, uint32_t lane) {
     uint16_t *st16 = (uint16_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
@@ -590,8 +718,7 @@ __device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32
         const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
         const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
         uint32_t ce, co;
-        words2(x, nx, ce, co);
-        bad |= overlong2_bits(x);
+        bad |= class_words<kClass>(x, nx, ce, co);
         if (j == 0) {
             ce0 = ce;
             co0 = co;
@@ -617,14 +744,13 @@ __device__ __forceinline__ bool scatter_words2(const LaneBytes &t, int r, uint32
             if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
         }
         has = p < 16;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if ((p >> 2) == (uint32_t)j) {
-                uint32_t ce, co;
-                words2(t.d[r][j], j < 3 ? t.d[r][j + 1] : nx_row, ce, co);
-                v = word_at2(ce, co, p & 3u);
-            }
-        }
+        const uint32_t j = p >> 2;
+        const uint32_t a0 = t.d[r][0], a1 = t.d[r][1], a2 = t.d[r][2], a3 = t.d[r][3];
+        const uint32_t x = j == 0 ? a0 : (j == 1 ? a1 : (j == 2 ? a2 : a3));
+        const uint32_t y = j == 0 ? a1 : (j == 1 ? a2 : (j == 2 ? a3 : nx_row));
+        uint32_t ce, co;
+        class_words<kClass>(x, y, ce, co);
+        v = word_at2(ce, co, p & 3u);
     }
     if (has) st16[o0] = (uint16_t)v;
     return bad != 0;
@@ -696,10 +822,13 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
             wlo = gend;
         }
         const uint32_t h = (uint32_t)(((uintptr_t)(out + u0) >> 1) & 7u);
-        if (kClass == kUpTo2) {   // words straight from the bytes
+        if constexpr (kClass == kUpTo2) {   // words straight from the bytes
 #pragma unroll
             for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
-                bad |= scatter_words2<kFull>(t, r, h + gof[r], wst, wbase, head, end, lane);
+                bad |= scatter_words<kClass, kFull>(t, r, h + gof[r], wst, wbase, head, end, lane);
+        } else if (kClass == kQuad && !kFull && !t.edge) {
+#pragma unroll
+            for (int r = g * kGroup; r < (g + 1) * kGroup; ++r) bad |= scatter_quad(t, r, h + gof[r], wst, lane);
         } else {
             if (g > 0 || !staged0)
 #pragma unroll
@@ -719,25 +848,6 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
     }
     flush_carry<2>(gend, wlo, wst, cy, lane);
     return bad;
-}
-
-// ------------------------------------------------------------------------
-// Validation only: value rules on every leading byte, from its byte and
-// the next (SWAR over the dword x, with y = the bytes one position later).
-// ------------------------------------------------------------------------
-template <uint32_t kClass>
-__device__ __forceinline__ uint32_t value_bits(uint32_t x, uint32_t y) {
-    uint32_t bad = zero_bytes((x & 0xFEFEFEFEu) ^ 0xC0C0C0C0u);            // C0, C1
-    if (kClass == kUpTo2) return bad;
-    const uint32_t y5 = y << 2;                                              // bit 5 of the next byte
-    bad |= zero_bytes(x ^ 0xE0E0E0E0u) & ~y5;                                // E0 80..9F: overlong
-    bad |= zero_bytes(x ^ 0xEDEDEDEDu) & y5;                                 // ED A0..BF: surrogate
-    if (kClass == kUpTo3) return bad;
-    const uint32_t y54 = (y << 2) | (y << 3);                                // bit 5 or 4 of the next byte
-    bad |= zero_bytes(x ^ 0xF0F0F0F0u) & ~y54;                               // F0 80..8F: overlong
-    bad |= zero_bytes(x ^ 0xF4F4F4F4u) & y54;                                // F4 90..BF: too large
-    bad |= ((x & 0x7F7F7F7Fu) + 0x0B0B0B0Bu) & x;                            // F5..FF
-    return bad & 0x80808080u;
 }
 
 // ------------------------------------------------------------------------
@@ -969,7 +1079,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (!moot && !direct) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
                 case kUpTo3: scatter_row<kUpTo3, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
-                case kQuad: scatter_row<kQuad, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
+                case kQuad:   // staged after the prefix, except at the ends and in batches
+                    if (kBatch || t.edge) scatter_row<kQuad, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane);
+                    break;
                 default: scatter_row<kAny, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
             }
             __syncthreads();   // the tile prefix is known
