@@ -64,7 +64,10 @@ def kernel_hash() -> str:
 # inputs
 # ---------------------------------------------------------------------------
 
-def generate(size: int):
+SERVE_REQUESTS = 10_000
+
+
+def generate(size: int, serve: bool = True):
     """All buffers of the workload (host numpy), generated before any GPU
     work so the generator can fork worker processes."""
     ex = ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("fork"))
@@ -79,8 +82,13 @@ def generate(size: int):
             bufs.append((mix, enc, "invalid", bad))
             log(f"generated {mix} {enc} ({time.time() - t0:.1f}s)")
     small = make_buffer("mix1m", 1 << 20, SEED_MIX1M)
+    reqs = None
+    if serve:
+        from workloads import make_requests
+        reqs = make_requests(SERVE_REQUESTS, executor=ex)
+        log(f"generated {SERVE_REQUESTS} serving requests ({time.time() - t0:.1f}s)")
     ex.shutdown()
-    return bufs, small
+    return bufs, small, reqs
 
 
 def cut_utf8(a: np.ndarray, n: int) -> np.ndarray:
@@ -209,6 +217,45 @@ def batch_leg(G, dev, stream, aux):
     aux["batch100k_speedup_vs_single_calls"] = round(tloop / t, 1)
 
 
+def serve_leg(reqs, aux):
+    """The serving workload: open-loop Poisson arrivals at 50 000 requests/s,
+    log-normal sizes (median 32 KiB, sigma ln(2^18)/6, 64 B..16 MiB), 50/50
+    directions, 0.5% invalid; replayed in wall-clock time, then all at once
+    (saturation)."""
+    from paper_2111_08692_amd.serve import Server
+    srv = Server(reqs, nstreams=4)
+    srv.run(time_scale=0.0)   # warm-up (allocator, workspaces)
+    for tag, scale in (("50k_rps", 1.0), ("burst", 0.0)):
+        res = srv.run(time_scale=scale)
+        assert np.all(res.status[~reqs.invalid] == 0), "valid request failed"
+        aux[f"serve_{tag}_p50_us"] = round(res.percentile_us(50), 1)
+        aux[f"serve_{tag}_p99_us"] = round(res.percentile_us(99), 1)
+        aux[f"serve_{tag}_GBps"] = round(res.gbps, 2)
+        aux[f"serve_{tag}_launches"] = res.launches
+    aux["serve_workload"] = (f"{reqs.arrival.size} requests, {int(reqs.size.sum())} bytes, Poisson 50k/s "
+                             "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
+                             "directions, 0.5% invalid; UTF-8 requests batched per pass, 4 streams")
+
+
+def host_leg(bufs, aux):
+    """Host-resident input and output: one 1 GiB buffer per direction (CJK
+    mix) through the chunked, pipelined host path (64 MiB chunks, 3
+    streams).  Bounded by PCIe and host copies, reported apart from the HBM
+    roofline."""
+    from paper_2111_08692_amd.host_pipeline import HostPipeline
+    p = HostPipeline(chunk_bytes=64 << 20, nstreams=3)
+    for mix, enc, kind, b in bufs:
+        if mix != "cjk" or kind != "valid":
+            continue
+        conv = p.convert_utf8_to_utf16le if enc == "utf-8" else p.convert_utf16le_to_utf8
+        conv(b.data[: (64 << 20) // b.data.itemsize])   # warm-up
+        st, cnt, out = conv(b.data)
+        assert st == 0
+        d = "8to16" if enc == "utf-8" else "16to8"
+        aux[f"host_pipeline_cjk_{d}_GBps"] = round(b.data.nbytes / p.last["seconds"] / 1e9, 2)
+        aux[f"host_pipeline_cjk_{d}_pcie_bytes"] = int(b.data.nbytes + out.nbytes)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,7 +290,7 @@ def main():
         return
 
     size = args.size_mib << 20
-    bufs, small = generate(size)
+    bufs, small, reqs = generate(size, serve=not args.no_aux)
 
     import torch
     import paper_2111_08692_amd as G
@@ -376,6 +423,10 @@ def main():
         one_mib_latency(G, small, dev, stream, res, aux)
         log("batched strings")
         batch_leg(G, dev, stream, aux)
+        log("serving")
+        serve_leg(reqs, aux)
+        log("host-resident pipeline")
+        host_leg(bufs, aux)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(bufs, args.cpu_sample_mib << 20)
 

@@ -1,0 +1,239 @@
+"""Continuous-batching transcoding server over the C ABI (one GPU).
+
+Requests arrive open-loop (each has an arrival time); the scheduler loop, on
+every pass:
+
+* takes the requests that have arrived and admits them while their output
+  fits in the output pool of their direction (HBM is reserved per request
+  for the conversion's worst case: 2 bytes per input byte for UTF-8 ->
+  UTF-16LE, 3 bytes per input unit for UTF-16LE -> UTF-8);
+* launches the admitted UTF-8 requests as ONE batched call (their payloads
+  lie back to back in device memory) and the admitted UTF-16 requests as
+  asynchronous single-buffer calls, on the next of ``nstreams`` streams, and
+  queues a device-to-host copy of their results behind them;
+* polls the events of the launches in flight, stamps the completion time of
+  every finished one, and frees output space in launch order (the pools
+  are rings).
+
+Latency is completion time minus arrival time; throughput is input bytes
+over the span from the first arrival to the last completion.  Every
+conversion runs in the library's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Deque, List, Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import convert_utf8_to_utf16le_batch_async, convert_utf16le_to_utf8_async, load, results_tensor
+
+
+@dataclass
+class _Flight:
+    event: torch.cuda.Event
+    ids: np.ndarray           # request ids of this launch
+    kind: int                 # 0: UTF-8 -> UTF-16LE, 1: the reverse
+    held: int                 # output pool bytes held until completion
+    done: bool = False
+
+
+@dataclass
+class ServeResult:
+    """Per request: status, count, output offset (units, in the output pool
+    of its direction) and latency (s); plus the run's totals."""
+    status: np.ndarray
+    count: np.ndarray
+    out_off: np.ndarray
+    latency: np.ndarray
+    span_s: float
+    input_bytes: int
+    launches: int
+    max_inflight: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def gbps(self) -> float:
+        return self.input_bytes / self.span_s / 1e9 if self.span_s > 0 else 0.0
+
+    def percentile_us(self, q: float) -> float:
+        return float(np.percentile(self.latency, q) * 1e6)
+
+
+class _Ring:
+    """Byte ring over an output pool; frees in allocation order."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.head = 0
+        self.used = 0
+
+    def alloc(self, nbytes: int) -> Optional[Tuple[int, int]]:
+        """(start, bytes charged) or None when it does not fit now."""
+        if nbytes > self.size:
+            raise ValueError("request larger than the output pool")
+        start, waste = self.head, 0
+        if start + nbytes > self.size:   # does not fit before the end: start over at 0
+            waste, start = self.size - start, 0
+        if self.used + waste + nbytes > self.size:
+            return None
+        self.used += waste + nbytes
+        self.head = start + nbytes
+        return start, waste + nbytes
+
+    def free(self, nbytes: int) -> None:
+        self.used -= nbytes
+
+
+class Server:
+    """Device-resident payload arenas, per-direction output pools and a
+    stream pool.  ``reqs`` is a ``workloads.RequestSet``."""
+
+    def __init__(self, reqs, nstreams: int = 4, pool_bytes: int = 4 << 30, max_inflight: int = 16,
+                 max_batch_bytes: int = 256 << 20, device: str = "cuda"):
+        load()
+        self.r = reqs
+        self.dev = torch.device(device)
+        self.n = int(reqs.arrival.size)
+        self.d8 = torch.from_numpy(reqs.data8).to(self.dev)
+        self.d16 = torch.from_numpy(reqs.data16.view(np.int16)).to(self.dev)
+        self.off8_dev = torch.from_numpy(reqs.off8).to(self.dev)
+        self.pool_bytes = int(pool_bytes)
+        self.out16 = torch.empty(self.pool_bytes // 2, dtype=torch.int16, device=self.dev)   # UTF-16 words
+        self.out8 = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.dev)         # UTF-8 bytes
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(nstreams)]          # default priority
+        self.max_inflight = max_inflight
+        self.max_batch_bytes = max_batch_bytes
+        n8, n16 = int(reqs.ids8.size), int(reqs.ids16.size)
+        # results by position in each direction's queue: device slots, pinned host copies
+        self.res16_dev = torch.zeros((max(n16, 1), 2), dtype=torch.int64, device=self.dev)
+        self.res8_host = torch.zeros((max(n8, 1), 2), dtype=torch.int64).pin_memory()
+        self.res16_host = torch.zeros((max(n16, 1), 2), dtype=torch.int64).pin_memory()
+        torch.cuda.synchronize()
+
+    def run(self, time_scale: float = 1.0) -> ServeResult:
+        """Serve every request once, replaying arrivals in wall-clock time
+        (``time_scale`` stretches the schedule)."""
+        r = self.r
+        n = self.n
+        arr = r.arrival * time_scale
+        arr8 = arr[r.ids8] if r.ids8.size else np.zeros(0)
+        arr16 = arr[r.ids16] if r.ids16.size else np.zeros(0)
+        out_off = np.full(n, -1, dtype=np.int64)
+        done_t = np.zeros(n)
+        rings = (_Ring(self.pool_bytes), _Ring(self.pool_bytes))
+        inflight: Deque[_Flight] = collections.deque()
+        batch_offsets = []   # (ids, device out_offsets, pool word base) of the batched launches
+        i8 = i16 = 0
+        finished = launches = max_inflight = si = 0
+        t0 = time.perf_counter()
+        while finished < n:
+            now = time.perf_counter() - t0
+            launched = False
+            # UTF-8 -> UTF-16LE: the arrived requests (up to the batch limit) in one batched call
+            if i8 < arr8.size and arr8[i8] <= now and len(inflight) < self.max_inflight:
+                j = max(int(np.searchsorted(arr8, now, side="right")), i8 + 1)
+                lim = int(np.searchsorted(r.off8, r.off8[i8] + self.max_batch_bytes, side="right")) - 1
+                j = min(j, max(lim, i8 + 1))
+                got = rings[0].alloc(2 * int(r.off8[j] - r.off8[i8]))
+                while got is None and j > i8 + 1:   # admit a shorter prefix of the queue
+                    j = i8 + (j - i8) // 2
+                    got = rings[0].alloc(2 * int(r.off8[j] - r.off8[i8]))
+                if got is not None:
+                    start, held = got
+                    k, nb = j - i8, int(r.off8[j] - r.off8[i8])
+                    s = self.streams[si % len(self.streams)]
+                    si += 1
+                    with torch.cuda.stream(s):
+                        offs = self.off8_dev[i8:j + 1] - int(r.off8[i8])
+                        oo = torch.empty(k + 1, dtype=torch.int64, device=self.dev)
+                        res = results_tensor(k, device=self.dev)
+                        out = self.out16[start // 2:start // 2 + nb] if nb else self.out16[:1]
+                        rc = convert_utf8_to_utf16le_batch_async(self.d8[int(r.off8[i8]):int(r.off8[j])], offs, out,
+                                                                 oo, res, out_cap=nb, stream=s)
+                        if rc != 0:
+                            raise RuntimeError(f"batched call failed: {rc}")
+                        self.res8_host[i8:j].copy_(res[:k], non_blocking=True)
+                        ev = torch.cuda.Event()
+                        ev.record(s)
+                    ids = r.ids8[i8:j]
+                    batch_offsets.append((ids, oo, start // 2))
+                    inflight.append(_Flight(ev, ids, 0, held))
+                    i8 = j
+                    launches += 1
+                    launched = True
+            # UTF-16LE -> UTF-8: the arrived requests as single-buffer calls on one stream
+            if i16 < arr16.size and arr16[i16] <= now and len(inflight) < self.max_inflight:
+                j = max(int(np.searchsorted(arr16, now, side="right")), i16 + 1)
+                s = self.streams[si % len(self.streams)]
+                si += 1
+                q0, held = i16, 0
+                with torch.cuda.stream(s):
+                    for q in range(i16, j):
+                        a, b = int(r.off16[q]), int(r.off16[q + 1])
+                        got = rings[1].alloc(3 * (b - a))
+                        if got is None:
+                            break
+                        start, h = got
+                        cap = 3 * (b - a)
+                        out = self.out8[start:start + cap] if cap else self.out8[:1]
+                        rc = convert_utf16le_to_utf8_async(self.d16[a:b], out, self.res16_dev[q], out_cap=cap,
+                                                           stream=s)
+                        if rc != 0:
+                            raise RuntimeError(f"call failed: {rc}")
+                        out_off[r.ids16[q]] = start
+                        held += h
+                        i16 = q + 1
+                    if i16 > q0:
+                        self.res16_host[q0:i16].copy_(self.res16_dev[q0:i16], non_blocking=True)
+                        ev = torch.cuda.Event()
+                        ev.record(s)
+                if i16 > q0:
+                    inflight.append(_Flight(ev, r.ids16[q0:i16], 1, held))
+                    launches += 1
+                    launched = True
+            max_inflight = max(max_inflight, len(inflight))
+            # completion stamps for every finished launch; space back in launch order
+            t = time.perf_counter() - t0
+            for f in inflight:
+                if not f.done and f.event.query():
+                    f.done = True
+                    done_t[f.ids] = t
+                    finished += f.ids.size
+            freed = False
+            while inflight and inflight[0].done:
+                f = inflight.popleft()
+                rings[f.kind].free(f.held)
+                freed = True
+            if not launched and not freed:
+                if inflight:
+                    time.sleep(0)
+                else:
+                    nxt = min(arr8[i8] if i8 < arr8.size else np.inf, arr16[i16] if i16 < arr16.size else np.inf)
+                    wait = nxt - (time.perf_counter() - t0)
+                    if wait > 0.0005:
+                        time.sleep(wait - 0.0003)
+        torch.cuda.synchronize()
+        for ids, oo, base in batch_offsets:
+            out_off[ids] = base + oo[:-1].cpu().numpy()
+        status = np.zeros(n, dtype=np.int32)
+        count = np.zeros(n, dtype=np.int64)
+        for ids, host, m in ((r.ids8, self.res8_host, r.ids8.size), (r.ids16, self.res16_host, r.ids16.size)):
+            v = host[:m].numpy()
+            st = (v[:, 0] & 0xFFFFFFFF).astype(np.int64)
+            status[ids] = np.where(st >= 1 << 31, st - (1 << 32), st).astype(np.int32)
+            count[ids] = v[:, 1]
+        latency = done_t - arr
+        span = float(done_t.max() - arr.min()) if n else 0.0
+        return ServeResult(status=status, count=count, out_off=out_off, latency=latency, span_s=span,
+                           input_bytes=int(r.size.sum()), launches=launches, max_inflight=max_inflight)
+
+    def output_of(self, res: ServeResult, rid: int) -> np.ndarray:
+        """The output units of request ``rid`` after ``run`` (a valid request)."""
+        cnt, o = int(res.count[rid]), int(res.out_off[rid])
+        if self.r.kind[rid] == 0:
+            return self.out16[o:o + cnt].cpu().numpy().view(np.uint16)
+        return self.out8[o:o + cnt].cpu().numpy()

@@ -354,3 +354,89 @@ def random_text(rng: np.random.Generator, mix: str, nchars: int, encoding: str =
     """Small helper: ``nchars`` characters of ``mix`` encoded as a numpy array."""
     b = _encode(draw_codepoints(rng, mix, nchars), encoding)
     return np.frombuffer(b, dtype=np.uint8 if encoding == "utf-8" else "<u2").copy()
+
+
+# --------------------------------------------------------------------------
+# Serving: an open-loop request stream
+# --------------------------------------------------------------------------
+
+@dataclass
+class RequestSet:
+    """Requests in arrival order.  ``kind`` 0 is UTF-8 -> UTF-16LE, 1 the
+    reverse.  The payloads of each kind lie back to back in ``data8`` /
+    ``data16`` in arrival order: request ``ids8[j]`` is
+    ``data8[off8[j]:off8[j+1]]`` (bytes), request ``ids16[j]`` is
+    ``data16[off16[j]:off16[j+1]]`` (16-bit units)."""
+    arrival: np.ndarray          # seconds after the start, ascending
+    kind: np.ndarray             # int8
+    size: np.ndarray             # payload bytes
+    mixes: List[str]
+    invalid: np.ndarray          # bool: one byte or unit was replaced
+    ids8: np.ndarray
+    off8: np.ndarray
+    data8: np.ndarray
+    ids16: np.ndarray
+    off16: np.ndarray
+    data16: np.ndarray
+
+
+def _char_start8(pool: np.ndarray, i: int) -> int:
+    while i < pool.size and (pool[i] & 0xC0) == 0x80:
+        i += 1
+    return i
+
+
+def _char_start16(pool: np.ndarray, i: int) -> int:
+    return i + 1 if i < pool.size and 0xDC00 <= pool[i] <= 0xDFFF else i
+
+
+def make_requests(n: int, rate: float = 50_000.0, seed: int = SEED_SERVE, median: float = 32768,
+                  sigma: float = math.log(2 ** 18) / 6, lo: int = 64, hi: int = 16 << 20,
+                  invalid_fraction: float = 0.005, pool_bytes: int = 32 << 20,
+                  mixes: Sequence[str] = SCRIPT_MIXES, executor=None) -> RequestSet:
+    """``n`` requests with Poisson arrivals at ``rate`` per second, log-normal
+    payload sizes (``median``, ``sigma``, clipped to [lo, hi]), direction
+    50/50, mix uniform, ``invalid_fraction`` with one replaced byte (0xFF) or
+    unit (a lone low surrogate).  Payloads are slices of one generated pool
+    per mix and encoding, cut at character boundaries."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    kind = rng.integers(0, 2, size=n).astype(np.int8)
+    size = lognormal_lengths(rng, n, median, sigma, lo, min(hi, pool_bytes // 2))
+    mix_idx = rng.integers(0, len(mixes), size=n)
+    invalid = rng.random(n) < invalid_fraction
+    pools8 = {m: make_buffer(m, pool_bytes, seed + 10 + k, executor=executor).data for k, m in enumerate(mixes)}
+    pools16 = {m: make_buffer(m, pool_bytes, seed + 20 + k, encoding="utf-16-le", executor=executor).data
+               for k, m in enumerate(mixes)}
+    parts8, parts16, ids8, ids16 = [], [], [], []
+    for i in range(n):
+        mix = mixes[int(mix_idx[i])]
+        if kind[i] == 0:
+            pool = pools8[mix]
+            a = _char_start8(pool, int(rng.integers(0, pool.size - size[i])))
+            b = _char_start8(pool, a + int(size[i]))
+            p = pool[a:b].copy()
+            if invalid[i] and p.size:
+                p[int(rng.integers(0, p.size))] = 0xFF
+            parts8.append(p)
+            ids8.append(i)
+        else:
+            pool = pools16[mix]
+            units = int(size[i]) // 2
+            a = _char_start16(pool, int(rng.integers(0, pool.size - units)))
+            b = _char_start16(pool, a + units)
+            p = pool[a:b].copy()
+            if invalid[i] and p.size:
+                p[int(rng.integers(0, p.size))] = 0xDC00
+            parts16.append(p)
+            ids16.append(i)
+        size[i] = p.nbytes
+    off8 = np.zeros(len(parts8) + 1, dtype=np.int64)
+    off8[1:] = np.cumsum([p.size for p in parts8])
+    off16 = np.zeros(len(parts16) + 1, dtype=np.int64)
+    off16[1:] = np.cumsum([p.size for p in parts16])
+    data8 = np.concatenate(parts8) if parts8 else np.zeros(0, np.uint8)
+    data16 = np.concatenate(parts16) if parts16 else np.zeros(0, np.uint16)
+    return RequestSet(arrival=arrival, kind=kind, size=size, mixes=[mixes[int(m)] for m in mix_idx],
+                      invalid=invalid, ids8=np.array(ids8, dtype=np.int64), off8=off8, data8=data8,
+                      ids16=np.array(ids16, dtype=np.int64), off16=off16, data16=data16)
