@@ -325,3 +325,71 @@ def test_scatter_write_order():
                 row[e:e + 20] = [0x80] * 20
             row = row[:1028]
         check_scatter(row, lo, hi, max(min(e, hi) - 4, 0))
+
+
+# 5. Write order of the packed path for waves of ASCII and four-byte
+#    characters (scatter_quad): in instruction k, every lane stores the
+#    first word of its position k (the byte, or the high surrogate of the
+#    character starting there) at the slot of its next leading byte and the
+#    low surrogate at the slot after; lanes of one instruction may land in
+#    any order.  Then each lane rewrites its first two slots: its first
+#    character's first word, then that character's low surrogate or the
+#    next character's first word.  Every slot of a valid row must hold the
+#    character's word, for both lane orders.  The words are computed here
+#    from the characters themselves (chr / encode), not from the kernel's
+#    packed formulas, so the formulas are checked too.
+
+def quad_words_at(b, q):
+    """(first word, low surrogate) the kernel computes at position q:
+    packed 16-bit formulas for a leading byte >= F0, the byte otherwise."""
+    a, bb, c, d = b[q], b[q + 1], b[q + 2], b[q + 3]
+    first = ((a * 256 + bb * 4 + (c >> 4) + 0xE5B8) & 0xFFFF) if a >= 0xF0 else a
+    low = ((c & 0x0F) * 64 + d + 0xDB80) & 0xFFFF
+    return first, low
+
+
+def test_quad_write_order():
+    rng = np.random.default_rng(12)
+    for trial in range(40):
+        cps = []
+        data = b""
+        while len(data) < 1024 + 16:
+            cp = int(rng.integers(0x20, 0x7F)) if rng.random() < 0.7 else int(rng.integers(0x10000, 0x110000))
+            cps.append(cp)
+            data += chr(cp).encode("utf-8")
+        b = list(data) + [0] * 8
+        lead = [(x & 0xC0) != 0x80 for x in b]
+        width = [int(lead[i]) + int(b[i] >= 0xF0) for i in range(len(b))]
+        lw = [sum(width[16 * L:16 * L + 16]) for L in range(64)]
+        base = [sum(lw[:L]) for L in range(64)]
+        for order in ("low", "high"):
+            o = list(base)
+            stage = {}
+            for k in range(16):
+                writes = []
+                for L in range(64):
+                    q = 16 * L + k
+                    first, low = quad_words_at(b, q)
+                    writes += [(L, o[L], first), (L, o[L] + 1, low)]
+                    o[L] += width[q]
+                for L, a, v in sorted(writes, key=lambda w: w[0], reverse=(order == "high")):
+                    stage[a] = v
+            for L in range(64):
+                pos = [16 * L + k for k in range(8) if lead[16 * L + k]]
+                if not pos or pos[0] >= 16 * L + 4:
+                    continue
+                p1 = pos[0]
+                stage[base[L]] = quad_words_at(b, p1)[0]
+                if b[p1] >= 0xF0:
+                    stage[base[L] + 1] = quad_words_at(b, p1)[1]
+                elif len(pos) > 1:
+                    stage[base[L] + 1] = quad_words_at(b, pos[1])[0]
+            ref = []
+            i = 0
+            for cp in cps:
+                if i >= 1024:
+                    break
+                ref += list(np.frombuffer(chr(cp).encode("utf-16-le"), dtype="<u2"))
+                i += len(chr(cp).encode("utf-8"))
+            total = sum(lw)
+            assert [stage.get(s) for s in range(total)] == [int(x) for x in ref[:total]], (trial, order)
