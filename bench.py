@@ -234,7 +234,7 @@ def serve_leg(reqs, aux):
         aux[f"serve_{tag}_launches"] = res.launches
     aux["serve_workload"] = (f"{reqs.arrival.size} requests, {int(reqs.size.sum())} bytes, Poisson 50k/s "
                              "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
-                             "directions, 0.5% invalid; UTF-8 requests batched per pass, 4 streams")
+                             "directions, 0.5% invalid; each direction batched per pass, 4 streams")
 
 
 def host_leg(bufs, aux):

@@ -190,6 +190,22 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
                                             uint64_t k, uint16_t *out, uint64_t out_cap,
                                             int64_t *out_offsets, utf_result *results, void *stream);
 
+/*
+ * UTF-16LE -> UTF-8 of k strings packed back to back in `in` (2-byte
+ * aligned), string i being in[offsets[i] .. offsets[i+1]) in 16-bit units,
+ * offsets[0] == 0, offsets[k] == m.  Each string is validated and
+ * converted on its own, as by convert_utf16le_to_utf8 (Section 3; a high
+ * surrogate at a string's end and a low surrogate at a string's start are
+ * unpaired whatever the neighbouring string holds).  out_offsets[i] (bytes)
+ * is the sum of utf8_length_from_utf16le of strings 0 .. i-1; results[i]
+ * is {UTF_OK, bytes}, {UTF_UNPAIRED_HIGH or _LOW, first error in units
+ * inside the string} or {UTF_OUTPUT_TOO_SMALL, bytes}.  Same conventions
+ * as the UTF-8 form otherwise.
+ */
+int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, const int64_t *offsets,
+                                            uint64_t k, uint8_t *out, uint64_t out_cap,
+                                            int64_t *out_offsets, utf_result *results, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Library state                                                          */
 /* ---------------------------------------------------------------------- */

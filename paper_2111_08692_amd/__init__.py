@@ -58,7 +58,7 @@ EXPORTS = (
     "convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "validate_utf16le_async", "utf16_length_from_utf8_async",
     "utf8_length_from_utf16le_async", "convert_utf8_to_utf16le_async",
-    "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async",
+    "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async", "convert_utf16le_to_utf8_batch_async",
     "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
 )
 
@@ -83,6 +83,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "convert_utf8_to_utf16le_async": ([P, U64, P, U64, P, P], I32),
         "convert_utf16le_to_utf8_async": ([P, U64, P, U64, P, P], I32),
         "convert_utf8_to_utf16le_batch_async": ([P, U64, P, U64, P, U64, P, P, P], I32),
+        "convert_utf16le_to_utf8_batch_async": ([P, U64, P, U64, P, U64, P, P, P], I32),
         "utfgpu_release_workspace": ([], I32),
         "utfgpu_version": ([], ctypes.c_char_p),
         "utfgpu_tile_bytes": ([], U64),
@@ -282,5 +283,24 @@ def convert_utf8_to_utf16le_batch_async(data, offsets, out, out_offsets, results
         raise ValueError("offsets needs k+1 entries, out_offsets k+1, results k")
     cap = out.numel() if out_cap is None else int(out_cap)
     return int(load().convert_utf8_to_utf16le_batch_async(
+        _ptr(data), data.numel(), offsets.data_ptr(), k, _ptr(out), cap, out_offsets.data_ptr(),
+        results.data_ptr(), _stream(stream)))
+
+
+def convert_utf16le_to_utf8_batch_async(data, offsets, out, out_offsets, results, out_cap=None,
+                                        stream=None) -> int:
+    """``data`` 2-byte elements; ``offsets`` int64[k+1] in 16-bit units;
+    ``out`` bytes; ``out_offsets`` int64[k+1] (bytes); ``results`` from
+    ``results_tensor(k)``."""
+    _dev(data, 2, "data")
+    _dev(offsets, 8, "offsets")
+    _dev(out_offsets, 8, "out_offsets")
+    _dev(out, 1, "out")
+    _dev(results, 8, "results")
+    k = offsets.numel() - 1
+    if k < 0 or out_offsets.numel() < k + 1 or results.numel() < 2 * k:
+        raise ValueError("offsets needs k+1 entries, out_offsets k+1, results k")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    return int(load().convert_utf16le_to_utf8_batch_async(
         _ptr(data), data.numel(), offsets.data_ptr(), k, _ptr(out), cap, out_offsets.data_ptr(),
         results.data_ptr(), _stream(stream)))

@@ -30,6 +30,10 @@ hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, 
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream);
+hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
+                              uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
+                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream);
 }  // namespace utfgpu
 
 using namespace utfgpu;
@@ -175,15 +179,16 @@ hipError_t grow(T **p, u64 *cap, u64 need, int fill, hipStream_t s) {
     return hipSuccess;
 }
 
-// Batched-call arrays for `ntiles` tiles and `k` strings.
-hipError_t get_batch(Workspace *w, u64 ntiles, u64 k, hipStream_t s) {
+// Batched-call arrays for `ntiles` tiles of `tile_units` positions and `k`
+// strings (block offsets per 32 positions cover both directions).
+hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 k, hipStream_t s) {
     hipError_t e;
     if (!w->bad) {
         if ((e = hipMalloc(&w->bad, sizeof(uint32_t))) != hipSuccess) return e;
     }
-    const u64 positions = ntiles * (u64)kTileBytes + 128;   // every tile and the chunk past the last
+    const u64 positions = ntiles * tile_units + 128;   // every tile and the chunk past the last
     if ((e = grow(&w->starts, &w->starts_words, positions / 32 + 2, 0, s)) != hipSuccess) return e;
-    if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 64 + 2, 0, s)) != hipSuccess) return e;
+    if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 32 + 2, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->tilepre, &w->tilepre_cap, ntiles + 1, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->serr, &w->serr_cap, k + 1, 0xFF, s)) != hipSuccess) return e;
     return hipSuccess;
@@ -440,10 +445,32 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     const u64 nt = n > 0 ? utf8_tiles_for(head, (long long)n) : 0;
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
-    if (get_batch(w, nt, k, s) != hipSuccess) return UTF_ERR_HIP;
+    if (get_batch(w, nt, kTileBytes, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (launch_utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
                           w->blockoff, w->tilepre, w->serr, w->bad, s) != hipSuccess)
+        return UTF_ERR_HIP;
+    return UTF_OK;
+}
+
+int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, const int64_t *offsets, uint64_t k,
+                                            uint8_t *out, uint64_t out_cap, int64_t *out_offsets,
+                                            utf_result *results, void *stream) {
+    int32_t c = check16(in, m);
+    if (c != UTF_OK) return c;
+    if (!offsets || !out_offsets || (k > 0 && !results)) return UTF_ERR_NULL;
+    if (!out && out_cap > 0) return UTF_ERR_NULL;
+    if (k >= UTF_MAX_BATCH_STRINGS) return UTF_ERR_TOO_BIG;
+    hipStream_t s = as_stream(stream);
+    if (k == 0) return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    const long long head = m > 0 ? head_bytes(in) / 2 : 0;
+    const u64 nt = m > 0 ? utf16_tiles_for(head, (long long)m) : 0;
+    Workspace *w;
+    if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
+    if (get_batch(w, nt, kTileBytes / 2, k, s) != hipSuccess) return UTF_ERR_HIP;
+    if (launch_utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
+                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
+                           w->blockoff, w->tilepre, w->serr, w->bad, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }

@@ -268,6 +268,34 @@ __device__ __forceinline__ u64 resolve_prefix(u64 *status, u64 t, u64 epoch, int
 }
 
 // ------------------------------------------------------------------------
+// Batched calls
+// ------------------------------------------------------------------------
+// Batched calls: k strings, string i occupying input units [offsets[i],
+// offsets[i+1]).  Outputs are compact: string i's output starts at the sum
+// of the length-query values of strings 0..i-1, which is the scan of the
+// per-unit widths at offsets[i], so one device-wide scan serves them all.
+struct BatchCtx {
+    const int64_t *offsets;   // k + 1 boundaries
+    u64 k;
+    const uint16_t *starts;   // bitmap over frame positions: a non-empty string starts here
+    uint16_t *blockoff;       // per block of the frame (64 bytes / 32 words): its output offset inside its tile
+    u64 *tilepre;             // per tile: output offset of the tile
+    u64 *serr;                // per string: min (position << 4 | kind), ~0 when valid
+};
+
+// The string that owns input unit p: the largest i with offsets[i] <= p
+// (an empty string owns no byte, and is never the largest such i).
+__device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 k, long long p) {
+    u64 lo = 0, hi = k;
+    while (hi - lo > 1) {
+        const u64 mid = (lo + hi) / 2;
+        if (offsets[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------
 // Write-out of staged output
 // ------------------------------------------------------------------------
 // The output occupies bytes [g0, g0 + nbytes) of global memory.  `stage`

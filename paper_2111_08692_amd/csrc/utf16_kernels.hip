@@ -221,6 +221,70 @@ __device__ __forceinline__ u64 lane_first_error16(const LaneUnits &t, long long 
     return ~0ull;
 }
 
+// ------------------------------------------------------------------------
+// Batched calls: a string start ends the pairing (a high word before it and
+// a low word at it are both unpaired).
+// ------------------------------------------------------------------------
+// Start bits of the lane's chunk of row r: bits 0..7 its words, bit 8 the
+// word after.  The bitmap covers every tile of the call and 64 words past.
+__device__ __forceinline__ uint32_t lane_starts16(const BatchCtx &bc, long long wbase, int r, uint32_t lane) {
+    const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+    const long long e = q0 >> 4;
+    const uint32_t v = (uint32_t)bc.starts[e] | ((uint32_t)bc.starts[e + 1] << 16);
+    return (v >> (uint32_t)(q0 & 15)) & 0x1FFu;
+}
+
+// Unpaired words of the lane's chunk of row r as bits 0..7 (words outside
+// the input read as zero and pair with nothing).
+__device__ __forceinline__ uint32_t unpaired_bits(const LaneUnits &t, int r, uint32_t lane, uint32_t sbits) {
+    uint32_t u[10];
+    u[0] = prev_word(t, r, lane) & 0xFC00u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) u[j + 1] = (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFC00u;
+    u[9] = next_word(t, r, lane) & 0xFC00u;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool at_start = (sbits >> j) & 1u, next_start = (sbits >> (j + 1)) & 1u;
+        const bool bad_hi = u[j + 1] == 0xD800u && (u[j + 2] != 0xDC00u || next_start);
+        const bool bad_lo = u[j + 1] == 0xDC00u && (u[j] != 0xD800u || at_start);
+        bad |= (uint32_t)(bad_hi || bad_lo) << j;
+    }
+    return bad;
+}
+
+// Each string's first unpaired word among the lane's positions goes to that
+// string's error word.
+__device__ __forceinline__ void lane_errors_batch(const LaneUnits &t, long long wbase, long long head, long long end,
+                                                  uint32_t lane, const BatchCtx &bc) {
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t sb = lane_starts16(bc, wbase, r, lane);
+        uint32_t bad = unpaired_bits(t, r, lane, sb);
+        const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
+        // select among values, never index the lane's words by a runtime index
+        // (that would keep them in memory instead of registers)
+        const uint32_t a0 = t.d[r][0], a1 = t.d[r][1], a2 = t.d[r][2], a3 = t.d[r][3];
+        int lastj = -100;
+        while (bad) {
+            const int j = __builtin_ctz(bad);
+            bad &= bad - 1u;
+            const long long q = q0 + j;
+            if (q < head || q >= end) continue;
+            // no string starts in (lastj, j]: the same string, already reported
+            if (lastj > -100 && ((sb >> (lastj + 1)) & ((1u << (j - lastj)) - 1u)) == 0) continue;
+            lastj = j;
+            const uint32_t dw = (uint32_t)j >> 1;
+            const uint32_t x = dw == 0 ? a0 : (dw == 1 ? a1 : (dw == 2 ? a2 : a3));
+            const uint32_t w = (x >> (16 * (j & 1))) & 0xFFFFu;
+            const long long pin = q - head;
+            const u64 idx = owner_string(bc.offsets, bc.k, pin);
+            min_agent(bc.serr + idx,
+                      ((u64)(pin - bc.offsets[idx]) << 4) | (is_high(w) ? kUnpairedHigh : kUnpairedLow));
+        }
+    }
+}
+
 // UTF-8 bytes of word u: b0, b1, b2 in output order (only the low byte of
 // each is meaningful) and their number; `pv` and `nx` are the words before
 // and after (used by surrogates).  No branches.
@@ -333,11 +397,10 @@ __device__ __forceinline__ void narrow_row(const LaneUnits &t, int r, uint32_t s
     }
 }
 
-template <bool kConvert>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(const uint8_t *__restrict__ frame, long long head,
-                                                             long long m, uint8_t *__restrict__ out, u64 out_cap,
-                                                             u64 *__restrict__ status, Ctrl *__restrict__ ctrl,
-                                                             u64 ntiles, int spin_limit) {
+template <bool kConvert, bool kBatch>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(
+    const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
+    u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords16 : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
     __shared__ u64 s_prefix;
@@ -359,8 +422,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // a wave holding an unpaired surrogate; when an error before it is
     // already known, its output (past the valid prefix) is not written and
     // its first error not located
-    const bool unpaired = cls == kAnyUnit && __ballot(lane_has_unpaired(t, lane)) != 0;
-    const bool moot = unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
+    bool lane_bad = false;
+    if (cls == kAnyUnit) {
+        if (kBatch) {
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) lane_bad |= unpaired_bits(t, r, lane, lane_starts16(bc, wbase, r, lane)) != 0;
+        } else {
+            lane_bad = lane_has_unpaired(t, lane);
+        }
+    }
+    const bool unpaired = cls == kAnyUnit && __ballot(lane_bad) != 0;
+    const bool moot = !kBatch && unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
 
     if (kConvert) {
         uint32_t off[kRows], rowbase[kRows + 1];
@@ -391,7 +463,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (lane == 0) {
                 s_prefix = prefix;
                 if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
+                if (kBatch) bc.tilepre[tile] = prefix;
             }
+        }
+        if (kBatch && (lane & 3u) == 0) {   // in-tile output offset of every 32-word block
+#pragma unroll
+            for (int r = 0; r < kRows; ++r)
+                bc.blockoff[(wbase + r * kRowUnits + 8 * (long long)lane) >> 5] =
+                    (uint16_t)(wave_off + rowbase[r] + off[r]);
         }
         __syncthreads();   // the tile prefix is known
         uint32_t *wst = stage + wave * kStageWords16;
@@ -432,6 +511,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (!moot) flush_carry<1>(gend, wstart, wst, cy, lane);
     }
 
+    if (kBatch) {   // per string
+        if (unpaired) lane_errors_batch(t, wbase, head, end, lane, bc);
+        return;
+    }
     // the first unpaired surrogate, unless an error before the wave is known
     if (unpaired && !moot && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
         u64 err = lane_first_error16(t, wbase, head, end, lane);
@@ -472,16 +555,89 @@ int partial_blocks(long long units, long long units_per_block);
 hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
                               u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
+    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     if (convert)
-        hipLaunchKernelGGL(utf16_tile_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head, m,
-                           out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+        hipLaunchKernelGGL((utf16_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     else
-        hipLaunchKernelGGL(utf16_tile_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame, head,
-                           m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit());
+        hipLaunchKernelGGL((utf16_tile_kernel<false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(ctrl, result, nullptr, convert ? kFinConvert : kFinValidate, (u64)m, out_cap, nullptr,
                            0, stream);
+}
+
+// ------------------------------------------------------------------------
+// Batched UTF-16LE -> UTF-8
+// ------------------------------------------------------------------------
+// Output offset (bytes) of input word p: the tile's offset, the offset of
+// p's 32-word block inside the tile, and the widths of the block's words
+// before p.
+__device__ u64 batch_out_offset16(const uint8_t *frame, long long head, long long m, const BatchCtx &bc, u64 total,
+                                  int64_t p) {
+    if (p >= m) return total;
+    const long long q = head + p;
+    u64 w = bc.tilepre[q / kTileUnits] + bc.blockoff[q >> 5];
+    for (long long c = q & ~31ll; c < q; c += 8) w += load_chunk_width8(frame, head, c + 8 < q ? c + 8 : q, c);
+    return w;
+}
+
+// Per string: output offsets, result, and the reset of its error word and
+// start bit for the next call.
+__global__ void batch_post16_kernel(const uint8_t *frame, long long head, long long m, BatchCtx bc, Ctrl *ctrl,
+                                    int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
+                                    uint32_t *starts) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > bc.k) return;
+    const bool ok = *bad == 0;
+    const u64 total = ld_agent(&ctrl->total);
+    const int64_t a = bc.offsets[i];
+    const u64 oa = ok ? batch_out_offset16(frame, head, m, bc, total, a) : 0;
+    out_offsets[i] = (int64_t)oa;
+    if (i == bc.k) return;
+    const int64_t b = bc.offsets[i + 1];
+    if (a >= 0 && b > a && b <= m) {   // the start bit the prep kernel set for this string
+        const u64 q = (u64)(head + a);
+        atomicAnd(starts + (q >> 5), ~(1u << (q & 31u)));
+    }
+    const u64 e = bc.serr[i];
+    bc.serr[i] = ~0ull;
+    results[i].pad = 0;
+    if (!ok) {
+        results[i].status = kErrOffsets;
+        results[i].count = 0;
+        return;
+    }
+    const u64 ob = batch_out_offset16(frame, head, m, bc, total, b);
+    if (e != ~0ull) {
+        results[i].status = (int32_t)(e & 15u);
+        results[i].count = e >> 4;
+    } else {
+        results[i].status = ob > out_cap ? (int32_t)kOutputTooSmall : (int32_t)kOk;
+        results[i].count = ob - oa;
+    }
+}
+
+hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
+                             uint32_t *bad, hipStream_t stream);
+
+hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
+                              uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
+                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream) {
+    hipError_t e = launch_batch_prep(offsets, k, head, m, starts, bad, stream);
+    if (e != hipSuccess) return e;
+    const u64 ntiles = utf16_tiles_for(head, m);
+    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr};
+    if (m > 0)
+        hipLaunchKernelGGL((utf16_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
+    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    hipLaunchKernelGGL(batch_post16_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, m, bc, ctrl, out_offsets,
+                       results, out_cap, (const uint32_t *)bad, starts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_finalize(ctrl, scratch_result, nullptr, kFinConvert, (u64)m, out_cap, nullptr, 0, stream);
 }
 
 hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,

@@ -39,19 +39,6 @@ enum : uint32_t { kAscii = 0, kUpTo2 = 1, kUpTo3 = 2, kQuad = 3, kAny = 4 };
 // Classes whose waves can hold four-byte characters (two slots each).
 constexpr bool has4(uint32_t cls) { return cls >= kQuad; }
 
-// Batched calls: k strings, string i occupying input bytes [offsets[i],
-// offsets[i+1]).  Outputs are compact: string i's words start at the sum of
-// the length-query values of strings 0..i-1, which is the scan of the
-// per-byte widths at offsets[i], so one device-wide scan serves them all.
-struct BatchCtx {
-    const int64_t *offsets;   // k + 1 boundaries
-    u64 k;
-    const uint16_t *starts;   // bitmap over frame positions: a non-empty string starts here
-    uint16_t *blockoff;       // per 64-byte block of the frame: its output offset inside its tile
-    u64 *tilepre;             // per tile: output offset of the tile
-    u64 *serr;                // per string: min (position << 4 | kind), ~0 when valid
-};
-
 // Slots one wave stages at a time (kGroup rows).  Valid input needs at most
 // one slot per byte of the group plus one: a group can end with the leading
 // byte of a four-byte character (two slots) whose continuation bytes lie
@@ -899,18 +886,6 @@ __device__ __noinline__ u64 exact_chunk(uint32_t v0, uint32_t v1, uint32_t v2, u
     return ((u64)(q0 + (long long)first - 4 - head) << 4) | kind;
 }
 
-// The string that owns input byte p: the largest i with offsets[i] <= p
-// (an empty string owns no byte, and is never the largest such i).
-__device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 k, long long p) {
-    u64 lo = 0, hi = k;
-    while (hi - lo > 1) {
-        const u64 mid = (lo + hi) / 2;
-        if (offsets[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // Batched form of exact_chunk: string starts act as buffer ends (a byte at
 // a start continues nothing before it), `sbits` bit i marks a start at
 // chunk position i - 16.  Each string's first flagged byte in the chunk is
@@ -1347,14 +1322,21 @@ __global__ void clear_u32_kernel(uint32_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
+// Clear the offsets flag and mark the string starts (both directions).
+hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
+                             uint32_t *bad, hipStream_t stream) {
+    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, bad);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream) {
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
-    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, bad);
-    hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_batch_prep(offsets, k, head, n, starts, bad, stream);
     if (e != hipSuccess) return e;
     const u64 ntiles = utf8_tiles_for(head, n);
     const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr};

@@ -5,12 +5,14 @@ every pass:
 
 * takes the requests that have arrived and admits them while their output
   fits in the output pool of their direction (HBM is reserved per request
-  for the conversion's worst case: 2 bytes per input byte for UTF-8 ->
-  UTF-16LE, 3 bytes per input unit for UTF-16LE -> UTF-8);
-* launches the admitted UTF-8 requests as ONE batched call (their payloads
-  lie back to back in device memory) and the admitted UTF-16 requests as
-  asynchronous single-buffer calls, on the next of ``nstreams`` streams, and
-  queues a device-to-host copy of their results behind them;
+  for the worst case of any input: 4 bytes per input byte for UTF-8 ->
+  UTF-16LE, since a byte >= F0 counts two words even in an invalid request
+  and the offsets of the requests after it include them; 3 bytes per input
+  unit for UTF-16LE -> UTF-8);
+* launches the admitted requests of each direction as ONE batched call
+  (their payloads lie back to back in device memory) on the next of
+  ``nstreams`` streams, and queues a device-to-host copy of their results
+  behind it;
 * polls the events of the launches in flight, stamps the completion time of
   every finished one, and frees output space in launch order (the pools
   are rings).
@@ -29,7 +31,7 @@ from typing import Deque, List, Optional, Tuple
 import numpy as np
 import torch
 
-from . import convert_utf8_to_utf16le_batch_async, convert_utf16le_to_utf8_async, load, results_tensor
+from . import convert_utf8_to_utf16le_batch_async, convert_utf16le_to_utf8_batch_async, load, results_tensor
 
 
 @dataclass
@@ -101,6 +103,7 @@ class Server:
         self.d8 = torch.from_numpy(reqs.data8).to(self.dev)
         self.d16 = torch.from_numpy(reqs.data16.view(np.int16)).to(self.dev)
         self.off8_dev = torch.from_numpy(reqs.off8).to(self.dev)
+        self.off16_dev = torch.from_numpy(reqs.off16).to(self.dev)
         self.pool_bytes = int(pool_bytes)
         self.out16 = torch.empty(self.pool_bytes // 2, dtype=torch.int16, device=self.dev)   # UTF-16 words
         self.out8 = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.dev)         # UTF-8 bytes
@@ -108,8 +111,7 @@ class Server:
         self.max_inflight = max_inflight
         self.max_batch_bytes = max_batch_bytes
         n8, n16 = int(reqs.ids8.size), int(reqs.ids16.size)
-        # results by position in each direction's queue: device slots, pinned host copies
-        self.res16_dev = torch.zeros((max(n16, 1), 2), dtype=torch.int64, device=self.dev)
+        # results by position in each direction's queue (pinned host copies)
         self.res8_host = torch.zeros((max(n8, 1), 2), dtype=torch.int64).pin_memory()
         self.res16_host = torch.zeros((max(n16, 1), 2), dtype=torch.int64).pin_memory()
         torch.cuda.synchronize()
@@ -127,74 +129,62 @@ class Server:
         rings = (_Ring(self.pool_bytes), _Ring(self.pool_bytes))
         inflight: Deque[_Flight] = collections.deque()
         batch_offsets = []   # (ids, device out_offsets, pool word base) of the batched launches
-        i8 = i16 = 0
+        queue = [{"arr": arr8, "off": r.off8, "off_dev": self.off8_dev, "ids": r.ids8, "host": self.res8_host,
+                  "next": 0},
+                 {"arr": arr16, "off": r.off16, "off_dev": self.off16_dev, "ids": r.ids16, "host": self.res16_host,
+                  "next": 0}]
         finished = launches = max_inflight = si = 0
         t0 = time.perf_counter()
         while finished < n:
             now = time.perf_counter() - t0
             launched = False
-            # UTF-8 -> UTF-16LE: the arrived requests (up to the batch limit) in one batched call
-            if i8 < arr8.size and arr8[i8] <= now and len(inflight) < self.max_inflight:
-                j = max(int(np.searchsorted(arr8, now, side="right")), i8 + 1)
-                lim = int(np.searchsorted(r.off8, r.off8[i8] + self.max_batch_bytes, side="right")) - 1
-                j = min(j, max(lim, i8 + 1))
-                got = rings[0].alloc(2 * int(r.off8[j] - r.off8[i8]))
-                while got is None and j > i8 + 1:   # admit a shorter prefix of the queue
-                    j = i8 + (j - i8) // 2
-                    got = rings[0].alloc(2 * int(r.off8[j] - r.off8[i8]))
-                if got is not None:
-                    start, held = got
-                    k, nb = j - i8, int(r.off8[j] - r.off8[i8])
-                    s = self.streams[si % len(self.streams)]
-                    si += 1
-                    with torch.cuda.stream(s):
-                        offs = self.off8_dev[i8:j + 1] - int(r.off8[i8])
-                        oo = torch.empty(k + 1, dtype=torch.int64, device=self.dev)
-                        res = results_tensor(k, device=self.dev)
-                        out = self.out16[start // 2:start // 2 + nb] if nb else self.out16[:1]
-                        rc = convert_utf8_to_utf16le_batch_async(self.d8[int(r.off8[i8]):int(r.off8[j])], offs, out,
-                                                                 oo, res, out_cap=nb, stream=s)
-                        if rc != 0:
-                            raise RuntimeError(f"batched call failed: {rc}")
-                        self.res8_host[i8:j].copy_(res[:k], non_blocking=True)
-                        ev = torch.cuda.Event()
-                        ev.record(s)
-                    ids = r.ids8[i8:j]
-                    batch_offsets.append((ids, oo, start // 2))
-                    inflight.append(_Flight(ev, ids, 0, held))
-                    i8 = j
-                    launches += 1
-                    launched = True
-            # UTF-16LE -> UTF-8: the arrived requests as single-buffer calls on one stream
-            if i16 < arr16.size and arr16[i16] <= now and len(inflight) < self.max_inflight:
-                j = max(int(np.searchsorted(arr16, now, side="right")), i16 + 1)
+            # each direction: the arrived requests (up to the batch limit) in one batched call
+            for kind in (0, 1):
+                q = queue[kind]
+                arr_k, off_k = q["arr"], q["off"]
+                i = q["next"]
+                if i >= arr_k.size or arr_k[i] > now or len(inflight) >= self.max_inflight:
+                    continue
+                # worst-case output bytes per input unit, for any input: a UTF-8
+                # byte >= F0 counts two words even in an invalid string, and the
+                # offsets of the strings after it include them
+                per_unit = 4 if kind == 0 else 3
+                j = max(int(np.searchsorted(arr_k, now, side="right")), i + 1)
+                lim = int(np.searchsorted(off_k, off_k[i] + self.max_batch_bytes // (1 + kind), side="right")) - 1
+                j = min(j, max(lim, i + 1))
+                got = rings[kind].alloc(per_unit * int(off_k[j] - off_k[i]))
+                while got is None and j > i + 1:   # admit a shorter prefix of the queue
+                    j = i + (j - i) // 2
+                    got = rings[kind].alloc(per_unit * int(off_k[j] - off_k[i]))
+                if got is None:
+                    continue
+                start, held = got
+                k, nu = j - i, int(off_k[j] - off_k[i])
                 s = self.streams[si % len(self.streams)]
                 si += 1
-                q0, held = i16, 0
                 with torch.cuda.stream(s):
-                    for q in range(i16, j):
-                        a, b = int(r.off16[q]), int(r.off16[q + 1])
-                        got = rings[1].alloc(3 * (b - a))
-                        if got is None:
-                            break
-                        start, h = got
-                        cap = 3 * (b - a)
-                        out = self.out8[start:start + cap] if cap else self.out8[:1]
-                        rc = convert_utf16le_to_utf8_async(self.d16[a:b], out, self.res16_dev[q], out_cap=cap,
-                                                           stream=s)
-                        if rc != 0:
-                            raise RuntimeError(f"call failed: {rc}")
-                        out_off[r.ids16[q]] = start
-                        held += h
-                        i16 = q + 1
-                    if i16 > q0:
-                        self.res16_host[q0:i16].copy_(self.res16_dev[q0:i16], non_blocking=True)
-                        ev = torch.cuda.Event()
-                        ev.record(s)
-                if i16 > q0:
-                    inflight.append(_Flight(ev, r.ids16[q0:i16], 1, held))
-                    launches += 1
-                    launched = True
+                    offs = q["off_dev"][i:j + 1] - int(off_k[i])
+                    oo = torch.empty(k + 1, dtype=torch.int64, device=self.dev)
+                    res = results_tensor(k, device=self.dev)
+                    if kind == 0:
+                        out = self.out16[start // 2:start // 2 + 2 * nu] if nu else self.out16[:1]
+                        rc = convert_utf8_to_utf16le_batch_async(self.d8[int(off_k[i]):int(off_k[j])], offs, out,
+                                                                 oo, res, out_cap=2 * nu, stream=s)
+                    else:
+                        out = self.out8[start:start + 3 * nu] if nu else self.out8[:1]
+                        rc = convert_utf16le_to_utf8_batch_async(self.d16[int(off_k[i]):int(off_k[j])], offs, out,
+                                                                 oo, res, out_cap=3 * nu, stream=s)
+                    if rc != 0:
+                        raise RuntimeError(f"batched call failed: {rc}")
+                    q["host"][i:j].copy_(res[:k], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(s)
+                ids = q["ids"][i:j]
+                batch_offsets.append((ids, oo, start // 2 if kind == 0 else start))
+                inflight.append(_Flight(ev, ids, kind, held))
+                q["next"] = j
+                launches += 1
+                launched = True
             max_inflight = max(max_inflight, len(inflight))
             # completion stamps for every finished launch; space back in launch order
             t = time.perf_counter() - t0
@@ -212,7 +202,7 @@ class Server:
                 if inflight:
                     time.sleep(0)
                 else:
-                    nxt = min(arr8[i8] if i8 < arr8.size else np.inf, arr16[i16] if i16 < arr16.size else np.inf)
+                    nxt = min(q["arr"][q["next"]] if q["next"] < q["arr"].size else np.inf for q in queue)
                     wait = nxt - (time.perf_counter() - t0)
                     if wait > 0.0005:
                         time.sleep(wait - 0.0003)

@@ -197,3 +197,111 @@ def test_full_size_batch(G, orc):
     16 B .. 1 MiB), one script mix each, 1% with one injected error."""
     b = make_batch()
     check_batch(G, orc, b.data, b.offsets, label="full")
+
+
+# ---------------------------------------------------------------------------
+# UTF-16LE -> UTF-8
+# ---------------------------------------------------------------------------
+
+def run_batch16(G, data, offsets, in_off=0, cap=None, out_off=0):
+    data = np.ascontiguousarray(data, dtype=np.uint16)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    k = offsets.size - 1
+    d = to_dev(data, in_off)
+    offs = torch.from_numpy(offsets).to("cuda")
+    cap = int(cap)
+    buf, out, sentinel = guarded_out(cap, 1, out_off)
+    oo = torch.full((k + 1,), -7, dtype=torch.int64, device="cuda")
+    res = G.results_tensor(k)
+    rc = G.convert_utf16le_to_utf8_batch_async(d, offs, out, oo, res, out_cap=cap)
+    torch.cuda.synchronize()
+    st, cnt = G.decode_results(res, k)
+    return rc, st, cnt, oo.cpu().numpy(), to_host(out, cap), to_host(buf, buf.numel()), sentinel
+
+
+def check_batch16(G, orc, data, offsets, in_off=0, cap=None, out_off=0, label=""):
+    data = np.ascontiguousarray(data, dtype=np.uint16)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    ost, ocnt, oout, ooff = orc.convert_utf16le_to_utf8_batch(data, offsets)
+    total = int(ooff[-1])
+    cap = total if cap is None else int(cap)
+    rc, st, cnt, goff, got, whole, sentinel = run_batch16(G, data, offsets, in_off, cap, out_off)
+    assert rc == 0, (label, rc)
+    assert np.array_equal(goff, ooff), (label, "out_offsets", int(np.argmax(goff != ooff)))
+    est = np.where((ost == O.OK) & (ooff[1:] > cap), O.OUTPUT_TOO_SMALL, ost)
+    bad = np.nonzero((st != est) | (cnt != ocnt))[0]
+    assert bad.size == 0, (label, "results", int(bad[0]), (int(st[bad[0]]), int(cnt[bad[0]])),
+                           (int(est[bad[0]]), int(ocnt[bad[0]])))
+    lens = np.diff(ooff)
+    valid_byte = np.repeat(ost == O.OK, lens)[:cap]
+    diff = np.nonzero(valid_byte & (got[:min(cap, total)] != oout[:cap]))[0] if total else np.zeros(0)
+    assert diff.size == 0, (label, "output byte", int(diff[0]))
+    assert np.all(whole[:out_off] == sentinel) and np.all(whole[out_off + cap:] == sentinel), (label, "guard")
+    return st
+
+
+def pack16(strings):
+    parts = [np.asarray(s, dtype=np.uint16) for s in strings]
+    offsets = np.zeros(len(parts) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([p.size for p in parts])
+    data = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint16)
+    return data, offsets
+
+
+def u16(text):
+    return list(np.frombuffer(text.encode("utf-16-le"), dtype="<u2"))
+
+
+def test_small_hand_cases16(G, orc):
+    smile = u16("😀")   # D83D DE00
+    strings = [[], u16("a"), [], u16("é€"), smile, smile[:1], smile[1:], u16("ab") + smile[:1],
+               smile[1:] + u16("cd"), [0xDC00], [0xD800], [0xD800, 0x41], [0x41, 0xDFFF], u16("plain " * 7), []]
+    data, offsets = pack16(strings)
+    st = check_batch16(G, orc, data, offsets, label="hand16")
+    assert st[5] == O.UNPAIRED_HIGH and st[6] == O.UNPAIRED_LOW and st[7] == O.UNPAIRED_HIGH
+    assert st[8] == O.UNPAIRED_LOW
+
+
+@pytest.mark.parametrize("mix", ["ascii", "latin", "cyrillic", "cjk", "emoji", "mix1m"])
+@pytest.mark.parametrize("median", [4, 60, 900])
+def test_generated_batches16(G, orc, mix, median):
+    b = make_batch(k=600, seed=SEED_BATCH + 31 + median, encoding="utf-16-le", median=median, sigma=1.2, lo=0,
+                   hi=40_000, error_fraction=0.2, mixes=(mix,))
+    check_batch16(G, orc, b.data, b.offsets, label=f"16/{mix}/{median}")
+
+
+def test_random_units_and_alignment16(G, orc):
+    rng = np.random.default_rng(78)
+    strings = []
+    vals = np.array([0x41, 0x7F, 0x80, 0x7FF, 0x800, 0xD7FF, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0xE000, 0xFFFF],
+                    np.uint16)
+    for i in range(4000):
+        n = int(rng.integers(0, 30))
+        if i % 3 == 0:
+            strings.append(rng.choice(vals, size=n))
+        else:
+            strings.append(random_text(rng, "emoji" if i % 2 else "mix1m", n, encoding="utf-16-le"))
+    data, offsets = pack16(strings)
+    for in_off in (0, 1, 5):
+        st = check_batch16(G, orc, data, offsets, in_off=in_off, out_off=in_off, label=f"rand16/{in_off}")
+    assert (st == O.OK).sum() > 1500 and (st != O.OK).sum() > 300
+    total = int(orc.convert_utf16le_to_utf8_batch(data, offsets)[3][-1])
+    for cap in (0, total // 2, total - 1):
+        check_batch16(G, orc, data, offsets, cap=cap, label=f"cap16/{cap}")
+
+
+def test_bad_offsets_then_good_call16(G, orc):
+    b = make_batch(k=400, seed=SEED_BATCH + 41, encoding="utf-16-le", median=100, sigma=1.0, lo=0, hi=5000,
+                   error_fraction=0.1)
+    dec = b.offsets.copy()
+    dec[11] = dec[10] - 1
+    rc, st, cnt, goff, *_ = run_batch16(G, b.data, dec, cap=3 * b.data.size)
+    assert rc == 0 and np.all(st == G.ERR_OFFSETS) and np.all(goff == 0)
+    check_batch16(G, orc, b.data, b.offsets, label="16 after bad offsets")
+    check_batch16(G, orc, b.data, b.offsets, label="16 again")
+
+
+def test_full_size_batch16(G, orc):
+    """100 000 UTF-16LE strings, the same length distribution as the UTF-8 batch."""
+    b = make_batch(encoding="utf-16-le")
+    check_batch16(G, orc, b.data, b.offsets, label="full16")

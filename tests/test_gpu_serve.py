@@ -24,7 +24,7 @@ def served(G):
     from paper_2111_08692_amd.serve import Server
     reqs = make_requests(1500, rate=50_000, median=2048, hi=256 << 10, invalid_fraction=0.05,
                          pool_bytes=4 << 20)
-    bound = max(2 * reqs.data8.size, 3 * reqs.data16.size) + (1 << 20)
+    bound = max(4 * reqs.data8.size, 3 * reqs.data16.size) + (1 << 20)
     srv = Server(reqs, nstreams=3, pool_bytes=bound, max_batch_bytes=1 << 20)
     res = srv.run()
     return reqs, srv, res
@@ -86,3 +86,23 @@ def test_burst_and_tight_pool(G):
         else:
             st, cnt, _ = G.convert_utf16le_to_utf8(torch.from_numpy(p.view(np.int16)).cuda())
         assert (res.status[rid], res.count[rid]) == (st, cnt), rid
+
+
+def test_invalid_request_widens_the_batch(G):
+    """An invalid UTF-8 request of bytes >= F0 counts two words per byte;
+    the valid requests batched after it must still get their whole output
+    (the pool reserves the worst case of any input)."""
+    from paper_2111_08692_amd.serve import Server
+    from workloads import RequestSet
+    p8 = [np.full(500, 0xF5, np.uint8), np.full(3000, 0x61, np.uint8), np.full(3000, 0x62, np.uint8)]
+    p16 = [np.full(10, 0x41, np.uint16)]
+    off8 = np.r_[0, np.cumsum([p.size for p in p8])].astype(np.int64)
+    off16 = np.r_[0, np.cumsum([p.size for p in p16])].astype(np.int64)
+    reqs = RequestSet(arrival=np.zeros(4), kind=np.array([0, 0, 0, 1], np.int8),
+                      size=np.array([500, 3000, 3000, 20]), mixes=["ascii"] * 4,
+                      invalid=np.array([True, False, False, False]), ids8=np.array([0, 1, 2]), off8=off8,
+                      data8=np.concatenate(p8), ids16=np.array([3]), off16=off16, data16=np.concatenate(p16))
+    srv = Server(reqs, nstreams=1, pool_bytes=1 << 20)
+    res = srv.run(time_scale=0.0)
+    assert list(res.status) == [1, 0, 0, 0] and list(res.count[1:]) == [3000, 3000, 10]
+    assert np.all(srv.output_of(res, 1) == 0x61) and np.all(srv.output_of(res, 2) == 0x62)
