@@ -29,11 +29,11 @@ hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);
 hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                             u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream);
+                             u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream);
 hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
                               uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                               Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream);
+                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream);
 }  // namespace utfgpu
 
 using namespace utfgpu;
@@ -80,6 +80,8 @@ struct Workspace {
     u64 tilepre_cap = 0;
     u64 *serr = nullptr;            // per string: first error (~0 between calls)
     u64 serr_cap = 0;
+    uint32_t *wavestr = nullptr;    // per wave span: owner string of its first position
+    u64 wavestr_cap = 0;
 };
 
 std::mutex g_mu;
@@ -98,6 +100,7 @@ void free_ws(Workspace *w) {
     if (w->blockoff) (void)hipFree(w->blockoff);
     if (w->tilepre) (void)hipFree(w->tilepre);
     if (w->serr) (void)hipFree(w->serr);
+    if (w->wavestr) (void)hipFree(w->wavestr);
     delete w;
 }
 
@@ -191,6 +194,7 @@ hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 k, hipStream_
     if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 32 + 2, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->tilepre, &w->tilepre_cap, ntiles + 1, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->serr, &w->serr_cap, k + 1, 0xFF, s)) != hipSuccess) return e;
+    if ((e = grow(&w->wavestr, &w->wavestr_cap, ntiles * kWaves + 2, 0, s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -448,7 +452,7 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     if (get_batch(w, nt, kTileBytes, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (launch_utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                          w->blockoff, w->tilepre, w->serr, w->bad, s) != hipSuccess)
+                          w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
@@ -470,7 +474,7 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (get_batch(w, nt, kTileBytes / 2, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (launch_utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
                            reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                           w->blockoff, w->tilepre, w->serr, w->bad, s) != hipSuccess)
+                           w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }

@@ -281,18 +281,27 @@ struct BatchCtx {
     uint16_t *blockoff;       // per block of the frame (64 bytes / 32 words): its output offset inside its tile
     u64 *tilepre;             // per tile: output offset of the tile
     u64 *serr;                // per string: min (position << 4 | kind), ~0 when valid
+    const uint32_t *wavestr;  // per wave span: the string owning its first position (one more entry at the end)
 };
 
 // The string that owns input unit p: the largest i with offsets[i] <= p
 // (an empty string owns no byte, and is never the largest such i).
-__device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 k, long long p) {
-    u64 lo = 0, hi = k;
+// Binary search in [lo, hi).
+__device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 lo, u64 hi, long long p) {
     while (hi - lo > 1) {
         const u64 mid = (lo + hi) / 2;
         if (offsets[mid] <= p) lo = mid;
         else hi = mid;
     }
     return lo;
+}
+
+// The owner of input unit p lying in wave span w or in the three units
+// before it: between the owners of spans w-1 and w+1.
+__device__ __forceinline__ u64 owner_near(const BatchCtx &bc, long long w, long long p) {
+    const u64 lo = bc.wavestr[w > 0 ? w - 1 : 0];
+    const u64 hi1 = (u64)bc.wavestr[w + 1] + 1;
+    return owner_string(bc.offsets, lo, hi1 < bc.k ? hi1 : bc.k, p);
 }
 
 // ------------------------------------------------------------------------

@@ -278,7 +278,7 @@ __device__ __forceinline__ void lane_errors_batch(const LaneUnits &t, long long 
             const uint32_t x = dw == 0 ? a0 : (dw == 1 ? a1 : (dw == 2 ? a2 : a3));
             const uint32_t w = (x >> (16 * (j & 1))) & 0xFFFFu;
             const long long pin = q - head;
-            const u64 idx = owner_string(bc.offsets, bc.k, pin);
+            const u64 idx = owner_near(bc, wbase / kWaveUnits, pin);
             min_agent(bc.serr + idx,
                       ((u64)(pin - bc.offsets[idx]) << 4) | (is_high(w) ? kUnpairedHigh : kUnpairedLow));
         }
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
-    const uint32_t wave = tid >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
     const u64 tile = blockIdx.x;
     const long long end = head + m;
     const long long wbase = (long long)tile * kTileUnits + (long long)wave * kWaveUnits;
@@ -555,7 +555,7 @@ int partial_blocks(long long units, long long units_per_block);
 hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
                               u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
-    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (convert)
         hipLaunchKernelGGL((utf16_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
@@ -620,16 +620,16 @@ __global__ void batch_post16_kernel(const uint8_t *frame, long long head, long l
 }
 
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
-                             uint32_t *bad, hipStream_t stream);
+                             uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream);
 
 hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
                               uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                               Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                              u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream) {
-    hipError_t e = launch_batch_prep(offsets, k, head, m, starts, bad, stream);
-    if (e != hipSuccess) return e;
+                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
-    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr};
+    hipError_t e = launch_batch_prep(offsets, k, head, m, starts, bad, kWaveUnits, wavestr, ntiles * kWaves, stream);
+    if (e != hipSuccess) return e;
+    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr, wavestr};
     if (m > 0)
         hipLaunchKernelGGL((utf16_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);

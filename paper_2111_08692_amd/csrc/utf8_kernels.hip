@@ -931,7 +931,7 @@ __device__ __forceinline__ void exact_chunk_batch(uint32_t v0, uint32_t v1, uint
             if (lastpos > -100 && ((sbits >> (17 + lastpos)) & ((1ull << (pos - lastpos)) - 1ull)) == 0) continue;
             lastpos = pos;
             const long long pin = q0 + pos - head;          // input position
-            const u64 idx = owner_string(bc.offsets, bc.k, pin);
+            const u64 idx = owner_near(bc, q0 / kWaveBytes, pin);
             // the byte and the three after it, bytes of the next string read as zero
             const uint32_t lo = i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : (i == 3 ? v3 : v4)));
             const uint32_t hi = i == 0 ? v1 : (i == 1 ? v2 : (i == 2 ? v3 : (i == 3 ? v4 : v5)));
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
-    const uint32_t wave = tid >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
     const long long end = head + n;
     const u64 tile = blockIdx.x;
     const long long wbase = (long long)tile * kTileBytes + (long long)wave * kWaveBytes;
@@ -1225,7 +1225,7 @@ u64 utf8_tiles_for(long long head, long long n) {
 hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
     const u64 ntiles = utf8_tiles_for(head, n);
-    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+    const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (convert)
         hipLaunchKernelGGL((utf8_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
@@ -1322,24 +1322,39 @@ __global__ void clear_u32_kernel(uint32_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-// Clear the offsets flag and mark the string starts (both directions).
+// The string owning the first position of every wave span (`span` units,
+// frame coordinates), and of the end: lets an error's owner be found among
+// the few strings near its wave.
+__global__ void batch_index_kernel(const int64_t *offsets, u64 k, long long head, long long n, long long span,
+                                   uint32_t *wavestr, u64 nspans) {
+    const u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > nspans) return;
+    long long p = (long long)w * span - head;
+    p = p < 0 ? 0 : (p >= n ? n - 1 : p);
+    wavestr[w] = (uint32_t)owner_string(offsets, 0, k, p);
+}
+
+// Clear the offsets flag, mark the string starts and index the wave spans
+// (both directions).
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
-                             uint32_t *bad, hipStream_t stream) {
+                             uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream) {
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, bad);
     hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad);
+    const unsigned ig = (unsigned)((nspans + 1 + pb - 1) / pb);
+    hipLaunchKernelGGL(batch_index_kernel, dim3(ig), dim3(pb), 0, stream, offsets, k, head, n, span, wavestr, nspans);
     return hipGetLastError();
 }
 
 hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                             u64 *tilepre, u64 *serr, uint32_t *bad, hipStream_t stream) {
+                             u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream) {
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
-    hipError_t e = launch_batch_prep(offsets, k, head, n, starts, bad, stream);
-    if (e != hipSuccess) return e;
     const u64 ntiles = utf8_tiles_for(head, n);
-    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr};
+    hipError_t e = launch_batch_prep(offsets, k, head, n, starts, bad, kWaveBytes, wavestr, ntiles * kWaves, stream);
+    if (e != hipSuccess) return e;
+    const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr, wavestr};
     if (n > 0)
         hipLaunchKernelGGL((utf8_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
