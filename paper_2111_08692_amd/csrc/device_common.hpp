@@ -181,8 +181,7 @@ __device__ __forceinline__ bool status_ready(u64 s, u64 epoch) {
 }
 
 // Exclusive prefix of tile t (t > 0), run by one whole wave.  A probe
-// reads a window of kLookK * 64 predecessors (kLookWindow by default):
-// lane j looks at tiles
+// reads a window of kLookK * 64 predecessors: lane j looks at tiles
 // t-1-kLookK*j-k, k = 0..kLookK-1.  The sum runs from the nearest
 // predecessor that carries an inclusive prefix, so only the tiles up to
 // that one must have published; if none in the window does, their
@@ -193,9 +192,9 @@ __device__ __forceinline__ bool status_ready(u64 s, u64 epoch) {
 // `spin_limit` probes, the wave computes its aggregate with `agg(tile)` (a
 // wave-wide call returning the same value in every lane) and publishes it
 // unless the owner has done so meanwhile.
-constexpr int kLookWindow = 2;   // statuses per lane and probe (128 predecessors)
+constexpr int kLookK = 2;
 
-template <int kLookK, class Agg>
+template <class Agg>
 __device__ __forceinline__ u64 lookback(u64 *status, long long t, u64 epoch, int spin_limit, Agg agg) {
     const uint32_t lane = lane_id();
     u64 excl = 0;
@@ -263,7 +262,7 @@ __device__ __forceinline__ u64 resolve_prefix(u64 *status, u64 t, u64 epoch, int
         return 0;
     }
     if (lane == 0) st_agent(status + t * kStatusStride, pack_status(kFlagAggregate, epoch, tile_total));
-    const u64 prefix = lookback<kLookWindow>(status, (long long)t, epoch, spin_limit, agg);
+    const u64 prefix = lookback(status, (long long)t, epoch, spin_limit, agg);
     if (lane == 0) st_agent(status + t * kStatusStride, pack_status(kFlagPrefix, epoch, prefix + tile_total));
     return prefix;
 }
