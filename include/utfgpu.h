@@ -178,7 +178,8 @@ int32_t convert_utf16le_to_utf8_async(const uint16_t *in, uint64_t m, uint8_t *o
  * {UTF_OUTPUT_TOO_SMALL, words} when the string's words do not all fit
  * below out_cap.  A valid string's words are exact; words in the range of
  * an invalid string are unspecified.  If `offsets` is not a partition of
- * the input every result is {UTF_ERR_OFFSETS, 0} and out_offsets holds 0s.
+ * the input every result is {UTF_ERR_OFFSETS, 0} and out_offsets holds 0s
+ * (k == 0 with n > 0: the call returns UTF_ERR_OFFSETS and enqueues nothing).
  *
  * Asynchronous on `stream`, like the *_async calls; every pointer except
  * the stream is device memory.  Returns UTF_OK when enqueued, or a negative

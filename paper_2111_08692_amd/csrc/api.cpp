@@ -444,7 +444,10 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     if (reinterpret_cast<uintptr_t>(out) & 1u) return UTF_ERR_ALIGN;
     if (k >= UTF_MAX_BATCH_STRINGS) return UTF_ERR_TOO_BIG;
     hipStream_t s = as_stream(stream);
-    if (k == 0) return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (k == 0) {   // no strings partition a non-empty input
+        if (n != 0) return UTF_ERR_OFFSETS;
+        return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    }
     const long long head = n > 0 ? head_bytes(in) : 0;
     const u64 nt = n > 0 ? utf8_tiles_for(head, (long long)n) : 0;
     Workspace *w;
@@ -466,7 +469,10 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (!out && out_cap > 0) return UTF_ERR_NULL;
     if (k >= UTF_MAX_BATCH_STRINGS) return UTF_ERR_TOO_BIG;
     hipStream_t s = as_stream(stream);
-    if (k == 0) return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (k == 0) {   // no strings partition a non-empty input
+        if (m != 0) return UTF_ERR_OFFSETS;
+        return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    }
     const long long head = m > 0 ? head_bytes(in) / 2 : 0;
     const u64 nt = m > 0 ? utf16_tiles_for(head, (long long)m) : 0;
     Workspace *w;

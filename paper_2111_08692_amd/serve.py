@@ -222,7 +222,9 @@ class Server:
                            input_bytes=int(r.size.sum()), launches=launches, max_inflight=max_inflight)
 
     def output_of(self, res: ServeResult, rid: int) -> np.ndarray:
-        """The output units of request ``rid`` after ``run`` (a valid request)."""
+        """The output units of request ``rid`` after ``run`` (a valid request;
+        only while later requests have not reused its space: the pools are
+        rings, so this holds when a run's outputs fit the pool)."""
         cnt, o = int(res.count[rid]), int(res.out_off[rid])
         if self.r.kind[rid] == 0:
             return self.out16[o:o + cnt].cpu().numpy().view(np.uint16)

@@ -100,6 +100,9 @@ def test_empty_batches(G, orc):
     assert G.convert_utf8_to_utf16le_batch_async(to_dev(data), offs, out, oo, res) == 0
     torch.cuda.synchronize()
     assert int(oo[0]) == 0
+    # k == 0 cannot partition a non-empty input
+    d1 = to_dev(np.frombuffer(b"abc", dtype=np.uint8))
+    assert G.convert_utf8_to_utf16le_batch_async(d1, offs, out, oo, res) == G.ERR_OFFSETS
     # k > 0 strings, all empty (n == 0)
     check_batch(G, orc, data, np.zeros(17, dtype=np.int64), label="all empty")
     # one long string == the single-buffer call
