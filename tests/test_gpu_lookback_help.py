@@ -1,7 +1,8 @@
 """The look-back's helping path: with UTFGPU_LOOKBACK_SPINS=0 a wave that
 finds a predecessor's status word missing computes that tile's aggregate
 itself at once.  Run in a child process (the knob is read once per
-process); every result must still match the oracle."""
+process); every result must still match the oracle, single buffers and
+batched strings alike."""
 import os
 import subprocess
 import sys
@@ -30,6 +31,32 @@ for mix in ("mix1m", "cjk", "emoji", "ascii"):
         u = torch.from_numpy(oout[:ocnt].view(np.int16)).to("cuda")
         st, cnt, back = G.convert_utf16le_to_utf8(u)
         assert (st, cnt) == (0, b.size) and np.array_equal(back[:cnt].cpu().numpy(), b), (mix, size)
+# batched calls through the same path, both directions
+from workloads.mixes import make_batch
+for enc in ("utf-8", "utf-16-le"):
+    bt = make_batch(k=3000, seed=777, encoding=enc, median=300, sigma=1.5, lo=0, hi=200_000, error_fraction=0.05)
+    k = bt.offsets.size - 1
+    offs = torch.from_numpy(bt.offsets).to("cuda")
+    oo = torch.empty(k + 1, dtype=torch.int64, device="cuda")
+    rs = G.results_tensor(k)
+    if enc == "utf-8":
+        d = torch.from_numpy(bt.data).to("cuda")
+        out = torch.empty(2 * bt.data.size, dtype=torch.int16, device="cuda")
+        assert G.convert_utf8_to_utf16le_batch_async(d, offs, out, oo, rs) == 0
+        ost, ocnt, oout, ooff = O.convert_utf8_to_utf16le_batch(bt.data, bt.offsets)
+        got = out.cpu().numpy().view(np.uint16)
+    else:
+        d = torch.from_numpy(bt.data.view(np.int16)).to("cuda")
+        out = torch.empty(3 * bt.data.size, dtype=torch.uint8, device="cuda")
+        assert G.convert_utf16le_to_utf8_batch_async(d, offs, out, oo, rs) == 0
+        ost, ocnt, oout, ooff = O.convert_utf16le_to_utf8_batch(bt.data, bt.offsets)
+        got = out.cpu().numpy()
+    torch.cuda.synchronize()
+    st, cnt = G.decode_results(rs, k)
+    assert np.array_equal(oo.cpu().numpy(), ooff), enc
+    assert np.array_equal(st, ost) and np.array_equal(cnt, ocnt), enc
+    valid = np.repeat(ost == O.OK, np.diff(ooff))
+    assert np.array_equal(got[:ooff[-1]][valid], oout[valid]), enc
 print("helping path ok", flush=True)
 '''
 
