@@ -75,7 +75,8 @@ enum {
     UTF_ERR_ALIGN = -2,
     UTF_ERR_TOO_BIG = -3,
     UTF_ERR_HIP = -4,
-    UTF_ERR_OFFSETS = -5      /* batched calls: offsets are not a partition of the input */
+    UTF_ERR_OFFSETS = -5,     /* batched calls: offsets are not a partition of the input */
+    UTF_ERR_ARG = -6          /* tuning calls: operation, size class or geometry out of range */
 };
 
 /* Largest supported input: 2^40 - 1 UTF-8 bytes, 2^38 - 1 UTF-16 words. */
@@ -218,12 +219,65 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
  */
 int32_t utfgpu_release_workspace(void);
 
+/* ---------------------------------------------------------------------- */
+/* Tile geometry and its tuning table                                     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * The validate and convert kernels are compiled for several tile
+ * geometries: a workgroup of `waves` wave64 waves, each lane of which loads
+ * `rows` 16-byte chunks, covers `tile_bytes` = waves * rows * 1024 input
+ * bytes (UTF-8 bytes, or UTF-16LE bytes: half as many words).  Geometry 0
+ * (8 waves x 4 rows, 32 KiB) is the default; smaller tiles put more
+ * workgroups on small inputs.  Every geometry computes the same results:
+ * the choice only changes speed.
+ *
+ * Which geometry a call uses is looked up in a process-wide table indexed by
+ * operation (UTF_OP_*) and input size class: the class of b input bytes is
+ * ceil(log2(b)) (0 for b <= 1), clamped to UTF_SIZE_CLASSES - 1; UTF-16
+ * inputs count 2 bytes per word and batched calls their whole input.  The
+ * table starts at geometry 0 everywhere.  The environment variable
+ * UTFGPU_GEOMETRY, set to a geometry index before the first call, overrides
+ * the table for the whole process.  The table is host state: these calls
+ * need no GPU, may be made from any thread and take effect on the next
+ * call that looks the table up (a call in flight keeps its geometry).
+ */
+enum {
+    UTF_OP_VALIDATE_UTF8 = 0,       /* validate_utf8[_async] */
+    UTF_OP_CONVERT_UTF8 = 1,        /* convert_utf8_to_utf16le[_async] */
+    UTF_OP_VALIDATE_UTF16LE = 2,    /* validate_utf16le[_async] */
+    UTF_OP_CONVERT_UTF16LE = 3,     /* convert_utf16le_to_utf8[_async] */
+    UTF_OP_BATCH_UTF8 = 4,          /* convert_utf8_to_utf16le_batch_async */
+    UTF_OP_BATCH_UTF16LE = 5,       /* convert_utf16le_to_utf8_batch_async */
+    UTF_OP_COUNT = 6
+};
+#define UTF_SIZE_CLASSES 64
+
+/* Number of compiled geometries (at least 1). */
+int32_t utfgpu_geometry_count(void);
+
+/* Shape of geometry g: any of the output pointers may be null.  UTF_OK, or
+ * UTF_ERR_ARG if g is out of range. */
+int32_t utfgpu_geometry(int32_t g, uint32_t *waves, uint32_t *rows, uint64_t *tile_bytes);
+
+/* Make calls of operation `op` whose input falls in `size_class` use
+ * geometry g (-1 restores the default).  UTF_OK or UTF_ERR_ARG. */
+int32_t utfgpu_set_geometry(int32_t op, int32_t size_class, int32_t g);
+
+/* The geometry such a call uses now (UTFGPU_GEOMETRY included), or
+ * UTF_ERR_ARG. */
+int32_t utfgpu_get_geometry(int32_t op, int32_t size_class);
+
+/* The size class of an input of `bytes` bytes. */
+int32_t utfgpu_size_class(uint64_t bytes);
+
 /* Library version string, e.g. "utfgpu 0.1 gfx950". */
 const char *utfgpu_version(void);
 
-/* Input bytes one workgroup of the validate/convert kernels covers (a tile
- * of UTF-8 bytes, or of UTF-16LE bytes: half as many words).  Informational:
- * tests use it to place inputs across tile boundaries.  Needs no GPU. */
+/* Input bytes one workgroup of the validate/convert kernels covers in the
+ * default geometry (a tile of UTF-8 bytes, or of UTF-16LE bytes: half as
+ * many words).  Informational: tests use it to place inputs across tile
+ * boundaries.  Needs no GPU. */
 uint64_t utfgpu_tile_bytes(void);
 
 #ifdef __cplusplus

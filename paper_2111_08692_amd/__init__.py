@@ -44,13 +44,24 @@ ERR_ALIGN = -2
 ERR_TOO_BIG = -3
 ERR_HIP = -4
 ERR_OFFSETS = -5
+ERR_ARG = -6
+
+# operations of the geometry tuning table
+OP_VALIDATE_UTF8 = 0
+OP_CONVERT_UTF8 = 1
+OP_VALIDATE_UTF16LE = 2
+OP_CONVERT_UTF16LE = 3
+OP_BATCH_UTF8 = 4
+OP_BATCH_UTF16LE = 5
+OP_COUNT = 6
+SIZE_CLASSES = 64
 
 STATUS_NAMES = {
     OK: "OK", TOO_SHORT: "TOO_SHORT", TOO_LONG: "TOO_LONG", OVERLONG: "OVERLONG",
     TOO_LARGE: "TOO_LARGE", SURROGATE: "SURROGATE", HEADER_BITS: "HEADER_BITS",
     UNPAIRED_HIGH: "UNPAIRED_HIGH", UNPAIRED_LOW: "UNPAIRED_LOW",
     OUTPUT_TOO_SMALL: "OUTPUT_TOO_SMALL", ERR_NULL: "ERR_NULL", ERR_ALIGN: "ERR_ALIGN",
-    ERR_TOO_BIG: "ERR_TOO_BIG", ERR_HIP: "ERR_HIP", ERR_OFFSETS: "ERR_OFFSETS",
+    ERR_TOO_BIG: "ERR_TOO_BIG", ERR_HIP: "ERR_HIP", ERR_OFFSETS: "ERR_OFFSETS", ERR_ARG: "ERR_ARG",
 }
 
 EXPORTS = (
@@ -60,6 +71,7 @@ EXPORTS = (
     "utf8_length_from_utf16le_async", "convert_utf8_to_utf16le_async",
     "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async", "convert_utf16le_to_utf8_batch_async",
     "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
+    "utfgpu_geometry_count", "utfgpu_geometry", "utfgpu_set_geometry", "utfgpu_get_geometry", "utfgpu_size_class",
 )
 
 
@@ -87,6 +99,11 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "utfgpu_release_workspace": ([], I32),
         "utfgpu_version": ([], ctypes.c_char_p),
         "utfgpu_tile_bytes": ([], U64),
+        "utfgpu_geometry_count": ([], I32),
+        "utfgpu_geometry": ([I32, P, P, P], I32),
+        "utfgpu_set_geometry": ([I32, I32, I32], I32),
+        "utfgpu_get_geometry": ([I32, I32], I32),
+        "utfgpu_size_class": ([U64], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -125,6 +142,35 @@ def tile_bytes() -> int:
 
 def release_workspace() -> int:
     return int(load().utfgpu_release_workspace())
+
+
+def geometries() -> list:
+    """``(waves, rows, tile_bytes)`` of every compiled tile geometry (index 0
+    is the default)."""
+    lib = load()
+    out = []
+    for g in range(int(lib.utfgpu_geometry_count())):
+        w, r, tb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        rc = lib.utfgpu_geometry(g, ctypes.byref(w), ctypes.byref(r), ctypes.byref(tb))
+        if rc != OK:
+            raise RuntimeError(f"utfgpu_geometry({g}) failed: {rc}")
+        out.append((int(w.value), int(r.value), int(tb.value)))
+    return out
+
+
+def set_geometry(op: int, size_class: int, g: int) -> int:
+    """Calls of ``op`` whose input falls in ``size_class`` use geometry ``g``
+    (-1: the default).  Returns the C status."""
+    return int(load().utfgpu_set_geometry(int(op), int(size_class), int(g)))
+
+
+def get_geometry(op: int, size_class: int) -> int:
+    return int(load().utfgpu_get_geometry(int(op), int(size_class)))
+
+
+def size_class(nbytes: int) -> int:
+    """The tuning-table size class of an input of ``nbytes`` bytes."""
+    return int(load().utfgpu_size_class(int(nbytes)))
 
 
 # ---------------------------------------------------------------------------

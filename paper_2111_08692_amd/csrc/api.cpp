@@ -5,6 +5,7 @@
 // slots), kernel launches and the synchronous result read-back.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -13,30 +14,98 @@
 #include "../../include/utfgpu.h"
 #include "device_common.hpp"
 
-namespace utfgpu {
-u64 utf8_tiles_for(long long head, long long n);
-u64 utf16_tiles_for(long long head, long long m);
-hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
-                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);
-hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
-                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);
-hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, u64 *partials, Ctrl *ctrl,
-                               u64 *result, hipStream_t stream);
-hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,
-                              u64 *result, hipStream_t stream);
-hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);
-hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);
-hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
-                             uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
-                             Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                             u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream);
-hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
-                              uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
-                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream);
-}  // namespace utfgpu
+// The launchers of every compiled tile geometry (C++ linkage; one build of
+// the kernel files per entry of geometries.def).
+#define UTF_GEOMETRY(NS, WAVES, ROWS)                                                                             \
+    namespace utfgpu {                                                                                           \
+    namespace NS {                                                                                               \
+    u64 build_tile_bytes();                                                                                      \
+    u64 utf8_tiles_for(long long head, long long n);                                                             \
+    u64 utf16_tiles_for(long long head, long long m);                                                            \
+    hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out, \
+                                 u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);   \
+    hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out, \
+                                  u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);  \
+    hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, u64 *partials, Ctrl *ctrl,  \
+                                   u64 *result, hipStream_t stream);                                             \
+    hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,   \
+                                  u64 *result, hipStream_t stream);                                              \
+    hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);                   \
+    hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);                                                \
+    hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets,       \
+                                 u64 k, uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,    \
+                                 u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,           \
+                                 uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr,  \
+                                 hipStream_t stream);                                                            \
+    hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets,      \
+                                  u64 k, uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,    \
+                                  u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,          \
+                                  uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad,                    \
+                                  uint32_t *wavestr, hipStream_t stream);                                        \
+    }                                                                                                            \
+    }
+#include "geometries.def"
+#undef UTF_GEOMETRY
 
 using namespace utfgpu;
+
+namespace {
+
+// One compiled geometry: its shape and its launchers.
+struct Geometry {
+    const char *name;
+    uint32_t waves, rows;
+    u64 (*tile_bytes)();
+    u64 (*utf8_tiles_for)(long long, long long);
+    u64 (*utf16_tiles_for)(long long, long long);
+    decltype(&utfgpu::g8x4::launch_utf8_tiles) utf8_tiles;
+    decltype(&utfgpu::g8x4::launch_utf16_tiles) utf16_tiles;
+    decltype(&utfgpu::g8x4::launch_utf8_batch) utf8_batch;
+    decltype(&utfgpu::g8x4::launch_utf16_batch) utf16_batch;
+};
+
+#define UTF_GEOMETRY(NS, WAVES, ROWS)                                                                         \
+    {#NS, WAVES, ROWS, &utfgpu::NS::build_tile_bytes, &utfgpu::NS::utf8_tiles_for,                             \
+     &utfgpu::NS::utf16_tiles_for, &utfgpu::NS::launch_utf8_tiles, &utfgpu::NS::launch_utf16_tiles,           \
+     &utfgpu::NS::launch_utf8_batch, &utfgpu::NS::launch_utf16_batch},
+const Geometry kGeometries[] = {
+#include "geometries.def"
+};
+#undef UTF_GEOMETRY
+constexpr int kNumGeometries = (int)(sizeof(kGeometries) / sizeof(kGeometries[0]));
+
+// The length reductions and result writers do not depend on the tile
+// geometry: the 8 x 4 build's serve every call.
+namespace base = utfgpu::g8x4;
+
+// Tuning table: per operation and input size class, 1 + the geometry index
+// (0: the default geometry).  Written by utfgpu_set_geometry, read once per
+// call; UTFGPU_GEOMETRY (an index) overrides it for the whole process.
+std::atomic<uint8_t> g_table[UTF_OP_COUNT][UTF_SIZE_CLASSES];
+
+int forced_geometry() {
+    static const int g = [] {
+        const char *e = std::getenv("UTFGPU_GEOMETRY");
+        if (!e || !*e) return -1;
+        const int v = std::atoi(e);
+        return v >= 0 && v < kNumGeometries ? v : -1;
+    }();
+    return g;
+}
+
+int size_class(u64 bytes) {
+    const int c = bytes <= 1 ? 0 : 64 - __builtin_clzll(bytes - 1);   // ceil(log2(bytes))
+    return c < UTF_SIZE_CLASSES ? c : UTF_SIZE_CLASSES - 1;
+}
+
+const Geometry &geometry_for(int op, u64 bytes) {
+    const int f = forced_geometry();
+    if (f >= 0) return kGeometries[f];
+    const int g = (int)g_table[op][size_class(bytes)].load(std::memory_order_relaxed) - 1;
+    return kGeometries[g > 0 && g < kNumGeometries ? g : 0];
+}
+
+}  // namespace
 
 int utfgpu::lookback_spin_limit() {
     static const int limit = [] {
@@ -182,9 +251,10 @@ hipError_t grow(T **p, u64 *cap, u64 need, int fill, hipStream_t s) {
     return hipSuccess;
 }
 
-// Batched-call arrays for `ntiles` tiles of `tile_units` positions and `k`
-// strings (block offsets per 32 positions cover both directions).
-hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 k, hipStream_t s) {
+// Batched-call arrays for `ntiles` tiles of `tile_units` positions in
+// `waves` wave spans each and `k` strings (block offsets per 32 positions
+// cover both directions).
+hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 waves, u64 k, hipStream_t s) {
     hipError_t e;
     if (!w->bad) {
         if ((e = hipMalloc(&w->bad, sizeof(uint32_t))) != hipSuccess) return e;
@@ -194,7 +264,7 @@ hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 k, hipStream_
     if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 32 + 2, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->tilepre, &w->tilepre_cap, ntiles + 1, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->serr, &w->serr_cap, k + 1, 0xFF, s)) != hipSuccess) return e;
-    if ((e = grow(&w->wavestr, &w->wavestr_cap, ntiles * kWaves + 2, 0, s)) != hipSuccess) return e;
+    if ((e = grow(&w->wavestr, &w->wavestr_cap, ntiles * waves + 2, 0, s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -233,11 +303,12 @@ inline long long head_bytes(const void *p) { return (long long)(reinterpret_cast
 int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 out_cap, DevResult *res,
                      hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in);
-    const u64 nt = utf8_tiles_for(head, (long long)n);
+    const Geometry &g = geometry_for(convert ? UTF_OP_CONVERT_UTF8 : UTF_OP_VALIDATE_UTF8, n);
+    const u64 nt = g.utf8_tiles_for(head, (long long)n);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (launch_utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, s) !=
+    if (g.utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, s) !=
         hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
@@ -247,11 +318,12 @@ int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 
 int32_t enqueue_utf16(bool convert, const uint16_t *in, u64 m, uint8_t *out, u64 out_cap, DevResult *res,
                       hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in) / 2;
-    const u64 nt = utf16_tiles_for(head, (long long)m);
+    const Geometry &g = geometry_for(convert ? UTF_OP_CONVERT_UTF16LE : UTF_OP_VALIDATE_UTF16LE, 2 * m);
+    const u64 nt = g.utf16_tiles_for(head, (long long)m);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (launch_utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, s) !=
+    if (g.utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, s) !=
         hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
@@ -326,7 +398,7 @@ uint64_t utf16_length_from_utf8(const uint8_t *in, uint64_t n, void *stream) {
     hipStream_t s = as_stream(stream);
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
-    if (launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, w->dlen, s) !=
+    if (base::launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, w->dlen, s) !=
         hipSuccess)
         return ~0ull;
     return read_len(w, s);
@@ -338,7 +410,7 @@ uint64_t utf8_length_from_utf16le(const uint16_t *in, uint64_t m, void *stream) 
     hipStream_t s = as_stream(stream);
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return ~0ull;
-    if (launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, w->dlen, s) !=
+    if (base::launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, w->dlen, s) !=
         hipSuccess)
         return ~0ull;
     return read_len(w, s);
@@ -350,7 +422,7 @@ int32_t validate_utf8_async(const uint8_t *in, uint64_t n, utf_result *result, v
     if (!result) return UTF_ERR_NULL;
     hipStream_t s = as_stream(stream);
     DevResult *r = reinterpret_cast<DevResult *>(result);
-    if (n == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (n == 0) return base::launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     return enqueue_utf8(false, in, n, nullptr, 0, r, s, &w);
 }
@@ -361,7 +433,7 @@ int32_t validate_utf16le_async(const uint16_t *in, uint64_t m, utf_result *resul
     if (!result) return UTF_ERR_NULL;
     hipStream_t s = as_stream(stream);
     DevResult *r = reinterpret_cast<DevResult *>(result);
-    if (m == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (m == 0) return base::launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     return enqueue_utf16(false, in, m, nullptr, 0, r, s, &w);
 }
@@ -374,7 +446,7 @@ int32_t convert_utf8_to_utf16le_async(const uint8_t *in, uint64_t n, uint16_t *o
     if (reinterpret_cast<uintptr_t>(out) & 1u) return UTF_ERR_ALIGN;
     hipStream_t s = as_stream(stream);
     DevResult *r = reinterpret_cast<DevResult *>(result);
-    if (n == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (n == 0) return base::launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     return enqueue_utf8(true, in, n, out, out_cap, r, s, &w);
 }
@@ -386,7 +458,7 @@ int32_t convert_utf16le_to_utf8_async(const uint16_t *in, uint64_t m, uint8_t *o
     if (!result || (!out && out_cap > 0)) return UTF_ERR_NULL;
     hipStream_t s = as_stream(stream);
     DevResult *r = reinterpret_cast<DevResult *>(result);
-    if (m == 0) return launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (m == 0) return base::launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     return enqueue_utf16(true, in, m, out, out_cap, r, s, &w);
 }
@@ -396,10 +468,10 @@ int32_t utf16_length_from_utf8_async(const uint8_t *in, uint64_t n, uint64_t *re
     if (c != UTF_OK) return c;
     if (!result) return UTF_ERR_NULL;
     hipStream_t s = as_stream(stream);
-    if (n == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (n == 0) return base::launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
-    return launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, result, s) ==
+    return base::launch_utf16_length(frame_of(in), head_bytes(in), (long long)n, w->partials, w->ctrl, result, s) ==
                    hipSuccess
                ? UTF_OK
                : UTF_ERR_HIP;
@@ -410,10 +482,10 @@ int32_t utf8_length_from_utf16le_async(const uint16_t *in, uint64_t m, uint64_t 
     if (c != UTF_OK) return c;
     if (!result) return UTF_ERR_NULL;
     hipStream_t s = as_stream(stream);
-    if (m == 0) return launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    if (m == 0) return base::launch_set_u64(result, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     Workspace *w;
     if (get_ws(s, 0, &w) != hipSuccess) return UTF_ERR_HIP;
-    return launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, result, s) ==
+    return base::launch_utf8_length(frame_of(in), head_bytes(in) / 2, (long long)m, w->partials, w->ctrl, result, s) ==
                    hipSuccess
                ? UTF_OK
                : UTF_ERR_HIP;
@@ -446,14 +518,15 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     hipStream_t s = as_stream(stream);
     if (k == 0) {   // no strings partition a non-empty input
         if (n != 0) return UTF_ERR_OFFSETS;
-        return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+        return base::launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     }
     const long long head = n > 0 ? head_bytes(in) : 0;
-    const u64 nt = n > 0 ? utf8_tiles_for(head, (long long)n) : 0;
+    const Geometry &g = geometry_for(UTF_OP_BATCH_UTF8, n);
+    const u64 nt = n > 0 ? g.utf8_tiles_for(head, (long long)n) : 0;
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
-    if (get_batch(w, nt, kTileBytes, k, s) != hipSuccess) return UTF_ERR_HIP;
-    if (launch_utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
+    if (get_batch(w, nt, g.tile_bytes(), g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
+    if (g.utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
                           w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
@@ -471,14 +544,15 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     hipStream_t s = as_stream(stream);
     if (k == 0) {   // no strings partition a non-empty input
         if (m != 0) return UTF_ERR_OFFSETS;
-        return launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+        return base::launch_set_u64(reinterpret_cast<u64 *>(out_offsets), 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
     }
     const long long head = m > 0 ? head_bytes(in) / 2 : 0;
-    const u64 nt = m > 0 ? utf16_tiles_for(head, (long long)m) : 0;
+    const Geometry &g = geometry_for(UTF_OP_BATCH_UTF16LE, 2 * m);
+    const u64 nt = m > 0 ? g.utf16_tiles_for(head, (long long)m) : 0;
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
-    if (get_batch(w, nt, kTileBytes / 2, k, s) != hipSuccess) return UTF_ERR_HIP;
-    if (launch_utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
+    if (get_batch(w, nt, g.tile_bytes() / 2, g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
+    if (g.utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
                            reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
                            w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
@@ -487,6 +561,33 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
 
 const char *utfgpu_version(void) { return "utfgpu 0.1 gfx950"; }
 
-uint64_t utfgpu_tile_bytes(void) { return (uint64_t)utfgpu::kTileBytes; }
+uint64_t utfgpu_tile_bytes(void) { return kGeometries[0].tile_bytes(); }
+
+int32_t utfgpu_geometry_count(void) { return kNumGeometries; }
+
+int32_t utfgpu_geometry(int32_t g, uint32_t *waves, uint32_t *rows, uint64_t *tile_bytes) {
+    if (g < 0 || g >= kNumGeometries) return UTF_ERR_ARG;
+    if (waves) *waves = kGeometries[g].waves;
+    if (rows) *rows = kGeometries[g].rows;
+    if (tile_bytes) *tile_bytes = kGeometries[g].tile_bytes();
+    return UTF_OK;
+}
+
+int32_t utfgpu_set_geometry(int32_t op, int32_t size_class, int32_t g) {
+    if (op < 0 || op >= UTF_OP_COUNT || size_class < 0 || size_class >= UTF_SIZE_CLASSES) return UTF_ERR_ARG;
+    if (g < -1 || g >= kNumGeometries) return UTF_ERR_ARG;
+    g_table[op][size_class].store((uint8_t)(g < 0 ? 0 : g + 1), std::memory_order_relaxed);
+    return UTF_OK;
+}
+
+int32_t utfgpu_get_geometry(int32_t op, int32_t size_class) {
+    if (op < 0 || op >= UTF_OP_COUNT || size_class < 0 || size_class >= UTF_SIZE_CLASSES) return UTF_ERR_ARG;
+    const int f = forced_geometry();
+    if (f >= 0) return f;
+    const int g = (int)g_table[op][size_class].load(std::memory_order_relaxed) - 1;
+    return g > 0 && g < kNumGeometries ? g : 0;
+}
+
+int32_t utfgpu_size_class(uint64_t bytes) { return size_class(bytes); }
 
 }  // extern "C"

@@ -29,20 +29,39 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The tile geometry is fixed per build of the kernel files, which are
+// compiled once per entry of geometries.def with UTF_GEOM (a namespace),
+// UTF_WAVES and UTF_ROWS set; the C ABI picks one build per call.  Without
+// them a file builds the default geometry.
+#ifndef UTF_GEOM
+#define UTF_GEOM g8x4
+#define UTF_WAVES 8
+#define UTF_ROWS 4
+#endif
+
 namespace utfgpu {
 
-// Tiles of 32 KiB in workgroups of eight waves: two workgroups fit on a
-// CU (the tile kernels are held to 128 VGPRs, four waves per SIMD), so
-// one's load latency and look-back wait overlap the other's work.
 constexpr int kWave = 64;
-constexpr int kWaves = 8;
-constexpr int kBlock = kWaves * kWave;             // 512 lanes
-constexpr int kRows = 4;
+constexpr int kChunk = 16;                         // bytes per lane and row
+
+namespace UTF_GEOM {
+
+// Default: tiles of 32 KiB in workgroups of eight waves; two workgroups fit
+// on a CU (the tile kernels are held to 128 VGPRs, four waves per SIMD), so
+// one's load latency and look-back wait overlap the other's work.  Smaller
+// builds trade per-tile work for more workgroups on small inputs.
+constexpr int kWaves = UTF_WAVES;
+constexpr int kBlock = kWaves * kWave;             // 512 lanes by default
+constexpr int kRows = UTF_ROWS;
 constexpr int kGroup = 1;                          // rows staged at a time
-constexpr int kChunk = 16;
 constexpr int kRowBytes = kWave * kChunk;          // 1024
-constexpr int kWaveBytes = kRows * kRowBytes;      // 4096
-constexpr int kTileBytes = kWaves * kWaveBytes;    // 32768
+constexpr int kWaveBytes = kRows * kRowBytes;      // 4096 by default
+constexpr int kTileBytes = kWaves * kWaveBytes;    // 32768 by default
+static_assert(kRows % 2 == 0 && kRows >= 2, "rows are scanned in pairs");
+static_assert(kBlock <= 1024, "workgroup size");
+
+}  // namespace UTF_GEOM
+
 constexpr int kMaxPartials = 2048;                 // workgroups of the length reductions
 
 // Status codes; the same values as the public header.
@@ -489,8 +508,10 @@ __device__ __forceinline__ void flush_carry(uintptr_t gend, uintptr_t wstart, ui
 // ------------------------------------------------------------------------
 enum : int { kFinValidate = 0, kFinConvert = 1, kFinLength = 2 };
 
+namespace UTF_GEOM {
 hipError_t launch_finalize(Ctrl *ctrl, DevResult *result, u64 *len_result, int mode, u64 n, u64 out_cap,
                            const u64 *partials, int npartials, hipStream_t stream);
+}  // namespace UTF_GEOM
 
 // Look-back probes before a wave computes a silent predecessor's aggregate
 // itself: UTFGPU_LOOKBACK_SPINS when set (0 exercises the helping path on

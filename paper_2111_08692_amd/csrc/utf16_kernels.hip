@@ -26,6 +26,7 @@
 #include "device_common.hpp"
 
 namespace utfgpu {
+namespace UTF_GEOM {
 
 constexpr int kRowUnits = kRowBytes / 2;       // 512 words per row
 constexpr int kWaveUnits = kWaveBytes / 2;     // 2048 words per wave
@@ -397,6 +398,10 @@ __device__ __forceinline__ void narrow_row(const LaneUnits &t, int r, uint32_t s
     }
 }
 
+// Batched calls keep each 32-word block's output offset inside its tile in
+// 16 bits: a tile emits at most three bytes per word.
+static_assert(3 * kTileUnits <= 65536, "16-bit block offsets");
+
 template <bool kConvert, bool kBatch>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
@@ -649,4 +654,5 @@ hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m,
     return launch_finalize(ctrl, nullptr, result, kFinLength, 0, 0, partials, nb, stream);
 }
 
+}  // namespace UTF_GEOM
 }  // namespace utfgpu

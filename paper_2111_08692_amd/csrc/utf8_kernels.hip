@@ -31,6 +31,7 @@
 #include "device_common.hpp"
 
 namespace utfgpu {
+namespace UTF_GEOM {
 
 // Byte class of a wave, over its own bytes and the three bytes before it.
 // kQuad: leading bytes only below 0x80 or from F0 on (ASCII text with
@@ -967,6 +968,10 @@ __device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) 
 // ------------------------------------------------------------------------
 // Validation and conversion: tile t = workgroup t.
 // ------------------------------------------------------------------------
+// Batched calls keep each 64-byte block's output offset inside its tile in
+// 16 bits: a tile emits at most one word per byte.
+static_assert(kTileBytes <= 65536, "16-bit block offsets");
+
 template <bool kConvert, bool kBatch>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf8_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long n, uint16_t *__restrict__ out, u64 out_cap,
@@ -1062,7 +1067,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
             if (direct) {
-                u64 slot[kRows];
+                static_assert(kRows <= 4, "direct_words takes at most four rows");
+                u64 slot[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) slot[r] = base + rowbase[(r / kGroup) * kGroup] + gof[r];
                 direct_words(frame, head, end, wbase, lane, slot[0], slot[1], slot[2], slot[3], out, out_cap);
@@ -1216,6 +1222,9 @@ __global__ void set_u64_kernel(u64 *r, u64 v) {
 // ------------------------------------------------------------------------
 // Host-side launchers (C++ linkage, used by the C ABI layer).
 // ------------------------------------------------------------------------
+// Input bytes per tile of this build.
+u64 build_tile_bytes() { return (u64)kTileBytes; }
+
 u64 utf8_tiles_for(long long head, long long n) {
     // three positions past the end belong to tiles too: a leading byte near
     // the end announces continuation bytes there
@@ -1397,4 +1406,5 @@ hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream) {
     return hipGetLastError();
 }
 
+}  // namespace UTF_GEOM
 }  // namespace utfgpu
