@@ -45,7 +45,7 @@ METRIC = "input GB/s validated+transcoded (UTF-8<->UTF-16LE) and % of HBM roofli
 HBM_PEAK_GBS = 8000.0
 ERROR_RATE = 1e-6
 KERNEL_SOURCES = ["paper_2111_08692_amd/csrc/device_common.hpp", "paper_2111_08692_amd/csrc/utf8_kernels.hip",
-                  "paper_2111_08692_amd/csrc/utf16_kernels.hip"]
+                  "paper_2111_08692_amd/csrc/utf16_kernels.hip", "paper_2111_08692_amd/csrc/geometries.def"]
 
 
 def log(*a):
@@ -235,6 +235,25 @@ def serve_leg(reqs, aux):
     aux["serve_workload"] = (f"{reqs.arrival.size} requests, {int(reqs.size.sum())} bytes, Poisson 50k/s "
                              "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
                              "directions, 0.5% invalid; each direction batched per pass, 4 streams")
+
+
+def tune_leg(small, aux):
+    """The geometry tuner on the 1 MiB mixed-script text, at four input
+    sizes: the geometry it picks and its speed-up over the default.  The
+    table is not installed (the other legs run the default geometry)."""
+    from paper_2111_08692_amd import tune
+    t0 = time.time()
+    res = tune.tune(small.data, ops=("convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
+                                     "convert_utf8_to_utf16le_batch", "convert_utf16le_to_utf8_batch"),
+                    sizes=(1 << 16, 1 << 20, 1 << 24, 1 << 28), min_ms=2.0, reps=3, install=False)
+    names = res["geometries"]
+    ops = {}
+    for op, rows in res["measured"].items():
+        ops[op] = {str(r["bytes"]): {"geometry": r["choice"], "default_us": r["us"][0],
+                                     "speedup": round(r["us"][0] / r["us"][names.index(r["choice"])], 3)}
+                   for r in rows}
+    aux["autotune"] = {"sample": "1 MiB mixed-script text, repeated; batched calls in strings of about 4 KiB",
+                       "geometries": names, "seconds": round(time.time() - t0, 1), "ops": ops}
 
 
 def host_leg(bufs, aux):
@@ -427,6 +446,8 @@ def main():
         serve_leg(reqs, aux)
         log("host-resident pipeline")
         host_leg(bufs, aux)
+        log("geometry tuner")
+        tune_leg(small, aux)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(bufs, args.cpu_sample_mib << 20)
 
@@ -447,7 +468,8 @@ def main():
                                "plus invalid variants (error rate 1e-6), UTF-8->UTF-16LE and UTF-16LE->UTF-8, "
                                "validating",
                    "buffers_per_step": len(bufs), "input_bytes_per_step": in_bytes,
-                   "buffer_bytes": size, "parallelism": "single GPU"},
+                   "buffer_bytes": size, "tile_geometry": "8 waves x 4 rows (32 KiB tiles, the default)",
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"per_buffer": per, "aux": aux, "kernel_hash": kernel_hash(),
