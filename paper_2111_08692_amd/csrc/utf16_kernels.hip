@@ -36,7 +36,11 @@ constexpr int kTileUnits = kTileBytes / 2;     // 32768 words per tile
 constexpr int kStageBytes16 = 3 * kRowUnits + 32;
 constexpr int kStageWords16 = kStageBytes16 / 4;   // a multiple of 4: stages stay 16-byte aligned
 
-enum : uint32_t { kAscii16 = 0, kUpTo2B = 1, kBmp = 2, kAnyUnit = 3 };
+// Wave classes by the words present: ASCII only; below 0x800; ASCII and
+// surrogates only (e.g. English with emoji: two bytes per surrogate word);
+// no surrogates; anything.
+enum : uint32_t { kAscii16 = 0, kUpTo2B = 1, kQuad16 = 2, kBmp = 3, kAnyUnit = 4 };
+__device__ __forceinline__ bool has_sur(uint32_t cls) { return cls == kQuad16 || cls == kAnyUnit; }
 
 // Zero the words of the dword holding frame words p, p+1 that fall
 // outside [lo, hi).
@@ -158,6 +162,7 @@ __device__ __forceinline__ uint32_t survey16(const LaneUnits &t, long long wbase
     else if (__ballot(a800 != 0)) cls = kBmp;
     else if (__ballot(a80 != 0)) cls = kUpTo2B;
     if (!kWidths) return cls;
+    bool other = false;   // a word >= 0x80 that is not a surrogate
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         uint32_t w = 8;
@@ -165,14 +170,22 @@ __device__ __forceinline__ uint32_t survey16(const LaneUnits &t, long long wbase
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t u0 = t.d[r][k] & 0xFFFFu, u1 = t.d[r][k] >> 16;
-                w += (u0 >= 0x80u) + (u1 >= 0x80u);
+                const bool g0 = u0 >= 0x80u, g1 = u1 >= 0x80u;
+                w += g0 + g1;
                 if (cls >= kBmp) w += (u0 >= 0x800u) + (u1 >= 0x800u);
-                if (cls == kAnyUnit) w -= (uint32_t)is_sur(u0) + (uint32_t)is_sur(u1);
+                if (cls == kAnyUnit) {
+                    const bool s0 = is_sur(u0), s1 = is_sur(u1);
+                    w -= (uint32_t)s0 + (uint32_t)s1;
+                    other = other || (g0 && !s0) || (g1 && !s1);
+                }
             }
         }
         if (t.edge) w -= outside_count8(wbase + r * kRowUnits + 8 * (long long)lane, head, end);
         width[r] = w;
     }
+    // ASCII and surrogates only: the same widths (two bytes a surrogate
+    // word), a cheaper encoder
+    if (cls == kAnyUnit && !__ballot(other)) cls = kQuad16;
     return cls;
 }
 
@@ -287,17 +300,43 @@ __device__ __forceinline__ void lane_errors_batch(const LaneUnits &t, long long 
 }
 
 // UTF-8 bytes of word u: b0, b1, b2 in output order (only the low byte of
-// each is meaningful) and their number; `pv` and `nx` are the words before
-// and after (used by surrogates).  No branches.
+// each is meaningful) and their number; `pv` is the word before (a low
+// surrogate takes two bits from it).  No branches.
+//
+// A surrogate pair hi, lo encodes v = 0x10000 + ((hi & 0x3FF) << 10 |
+// (lo & 0x3FF)) in four bytes.  Since the low 12 bits of 0x10000 are zero,
+// v >> 12 = 0x10 + ((hi >> 2) & 0xFF): the high word alone gives the first
+// two bytes, F0 | (v >> 18) and 80 | ((v >> 12) & 3F); the low word gives
+// 80 | (hi & 3) << 4 | ((lo >> 6) & 0xF) and 80 | (lo & 3F).
 template <uint32_t kClass>
-__device__ __forceinline__ void encode_word(uint32_t u, uint32_t pv, uint32_t nx, uint32_t &b0, uint32_t &b1,
-                                            uint32_t &b2, uint32_t &len) {
+__device__ __forceinline__ void encode_word(uint32_t u, uint32_t pv, uint32_t &b0, uint32_t &b1, uint32_t &b2,
+                                            uint32_t &len) {
     const bool c1 = u >= 0x80u;
     const uint32_t t6 = u >> 6;
     const uint32_t last = (u & 0x3Fu) | 0x80u;            // last byte of a 2- or 3-byte sequence
+    b2 = last;
+    if (kClass == kQuad16 || kClass == kAnyUnit) {
+        const uint32_t v12 = ((u >> 2) & 0xFFu) + 0x10u;
+        const uint32_t h0 = (v12 >> 6) | 0xF0u, h1 = (v12 & 0x3Fu) | 0x80u;
+        const uint32_t l0 = ((pv & 3u) << 4) | (t6 & 0xFu) | 0x80u;
+        const bool hi = (u & 0xFC00u) == 0xD800u;
+        const uint32_t s0 = hi ? h0 : l0, s1 = hi ? h1 : last;
+        if (kClass == kQuad16) {   // a word >= 0x80 is a surrogate
+            b0 = c1 ? s0 : u;
+            b1 = s1;
+            len = 1u + c1;
+            return;
+        }
+        const bool c2 = u >= 0x800u, sur = (u & 0xF800u) == 0xD800u;
+        b0 = c2 ? ((u >> 12) | 0xE0u) : (c1 ? (t6 | 0xC0u) : u);
+        b1 = c2 ? ((t6 & 0x3Fu) | 0x80u) : last;
+        b0 = sur ? s0 : b0;
+        b1 = sur ? s1 : b1;
+        len = sur ? 2u : 1u + c1 + c2;
+        return;
+    }
     b0 = c1 ? (t6 | 0xC0u) : u;                           // 2-byte lead (or the ASCII byte)
     b1 = last;
-    b2 = last;
     if (kClass == kUpTo2B) {
         len = 1u + c1;
         return;
@@ -306,24 +345,11 @@ __device__ __forceinline__ void encode_word(uint32_t u, uint32_t pv, uint32_t nx
     b0 = c2 ? ((u >> 12) | 0xE0u) : b0;
     b1 = c2 ? ((t6 & 0x3Fu) | 0x80u) : b1;
     len = 1u + c1 + c2;
-    if (kClass == kBmp) return;
-    // surrogates: the high word writes F0|.., 80|.. of the pair's code
-    // point, the low word the last two bytes
-    const bool hi = (u & 0xFC00u) == 0xD800u, sur = (u & 0xF800u) == 0xD800u;
-    const uint32_t h10 = (hi ? u : pv) & 0x3FFu, l10 = (hi ? nx : u) & 0x3FFu;
-    const uint32_t cp = 0x10000u + ((h10 << 10) | l10);
-    const uint32_t s0 = hi ? ((cp >> 18) | 0xF0u) : (((cp >> 6) & 0x3Fu) | 0x80u);
-    const uint32_t s1 = hi ? (((cp >> 12) & 0x3Fu) | 0x80u) : ((cp & 0x3Fu) | 0x80u);
-    b0 = sur ? s0 : b0;
-    b1 = sur ? s1 : b1;
-    len = sur ? 2u : len;
 }
 
-// Word j of the lane's chunk of row r, with j = -1 and j = 8 the words
-// before and after it.
-__device__ __forceinline__ uint32_t word_of(const LaneUnits &t, int r, int j, uint32_t pv, uint32_t nx) {
+// Word j of the lane's chunk of row r, with j = -1 the word before it.
+__device__ __forceinline__ uint32_t word_of(const LaneUnits &t, int r, int j, uint32_t pv) {
     if (j < 0) return pv;
-    if (j > 7) return nx;
     return (t.d[r][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
 }
 
@@ -333,8 +359,7 @@ __device__ __forceinline__ uint32_t word_of(const LaneUnits &t, int r, int j, ui
 template <uint32_t kClass, bool kEdge>
 __device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o, uint8_t *st, long long wbase,
                                            long long head, long long end, uint32_t lane) {
-    const uint32_t pv = kClass == kAnyUnit ? prev_word(t, r, lane) : 0u;
-    const uint32_t nx = kClass == kAnyUnit ? next_word(t, r, lane) : 0u;
+    const uint32_t pv = has_sur(kClass) ? prev_word(t, r, lane) : 0u;
     uint32_t in = 0xFFu;   // words of the chunk inside the input
     if (kEdge) {
         const long long q0 = wbase + r * kRowUnits + 8 * (long long)lane;
@@ -348,12 +373,11 @@ __device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         uint32_t b0, b1, b2, len;
-        encode_word<kClass>(word_of(t, r, j, pv, nx), word_of(t, r, j - 1, pv, nx), word_of(t, r, j + 1, pv, nx),
-                            b0, b1, b2, len);
+        encode_word<kClass>(word_of(t, r, j, pv), word_of(t, r, j - 1, pv), b0, b1, b2, len);
         if (kEdge && !((in >> j) & 1u)) len = 0;
         st[o] = (uint8_t)b0;
         st[o + 1] = (uint8_t)b1;
-        if (kClass != kUpTo2B) st[o + 2] = (uint8_t)b2;
+        if (kClass != kUpTo2B && kClass != kQuad16) st[o + 2] = (uint8_t)b2;   // at most two bytes a word there
         if (!kEdge) {
             if (j == 0) {
                 first = (b0 & 0xFFu) | ((b1 & 0xFFu) << 8);
@@ -428,7 +452,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // already known, its output (past the valid prefix) is not written and
     // its first error not located
     bool lane_bad = false;
-    if (cls == kAnyUnit) {
+    if (has_sur(cls)) {
         if (kBatch) {
 #pragma unroll
             for (int r = 0; r < kRows; ++r) lane_bad |= unpaired_bits(t, r, lane, lane_starts16(bc, wbase, r, lane)) != 0;
@@ -436,7 +460,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             lane_bad = lane_has_unpaired(t, lane);
         }
     }
-    const bool unpaired = cls == kAnyUnit && __ballot(lane_bad) != 0;
+    const bool unpaired = has_sur(cls) && __ballot(lane_bad) != 0;
     const bool moot = !kBatch && unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
 
     if (kConvert) {
@@ -496,12 +520,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 switch (cls) {
                     case kAscii16: narrow_row(t, r, s, wst, lane); break;
                     case kUpTo2B: encode_row<kUpTo2B, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    case kQuad16: encode_row<kQuad16, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                     case kBmp: encode_row<kBmp, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                     default: encode_row<kAnyUnit, false>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                 }
             } else {   // waves at the ends of the input (never all-ASCII)
                 switch (cls) {
                     case kUpTo2B: encode_row<kUpTo2B, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
+                    case kQuad16: encode_row<kQuad16, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                     case kBmp: encode_row<kBmp, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                     default: encode_row<kAnyUnit, true>(t, r, s + off[r], wst8, wbase, head, end, lane); break;
                 }

@@ -393,3 +393,20 @@ def test_quad_write_order():
                 i += len(chr(cp).encode("utf-8"))
             total = sum(lw)
             assert [stage.get(s) for s in range(total)] == [int(x) for x in ref[:total]], (trial, order)
+
+
+def test_surrogate_pair_bytes_split_by_word():
+    """The UTF-16 -> UTF-8 kernels encode a surrogate pair word by word: the
+    high word alone gives the first two bytes (through v >> 12 =
+    0x10 + ((hi >> 2) & 0xFF)) and the low word the last two, with two bits
+    (hi & 3) taken from the word before it.  Every pair, against Python's
+    own encoder."""
+    hi = np.repeat(np.arange(0xD800, 0xDC00, dtype=np.uint32), 1024)
+    lo = np.tile(np.arange(0xDC00, 0xE000, dtype=np.uint32), 1024)
+    v12 = ((hi >> 2) & 0xFF) + 0x10
+    got = np.stack([(v12 >> 6) | 0xF0, (v12 & 0x3F) | 0x80,
+                    ((hi & 3) << 4) | ((lo >> 6) & 0xF) | 0x80, (lo & 0x3F) | 0x80], axis=1).astype(np.uint8)
+    cp = 0x10000 + ((hi & 0x3FF) << 10 | (lo & 0x3FF))
+    text = "".join(map(chr, cp.tolist()))
+    want = np.frombuffer(text.encode("utf-8"), dtype=np.uint8).reshape(-1, 4)
+    assert np.array_equal(got, want)

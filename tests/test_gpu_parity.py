@@ -185,6 +185,27 @@ def test_boundary_straddle_utf16(G, orc, filler):
                 check_utf16(G, orc, np.concatenate([pre, p]).astype(np.uint16), label=f"end {bnd}{delta:+d} {p}")
 
 
+def test_ascii_and_surrogate_waves_utf16(G, orc):
+    """Waves holding only ASCII words and surrogates take their own encoder:
+    pairs straddling dword, lane, row and wave boundaries (ASCII shifts of
+    0..9 words), an unpaired high or low word or a reversed pair at those
+    places, and one word of another script that makes the wave general."""
+    rng = np.random.default_rng(21)
+    base = random_text(rng, "emoji", 6000, encoding="utf-16-le")
+    assert np.all((base < 0x80) | ((base & 0xF800) == 0xD800))
+    for shift in range(10):
+        data = np.concatenate([np.full(shift, 0x61, dtype=np.uint16), base]).astype(np.uint16)
+        check_utf16(G, orc, data, label=f"shift {shift}")
+    smile = [0xD83D, 0xDE00]
+    for bnd in (7, 8, 512, 2048, 4096):
+        for delta in (-2, -1, 0, 1):
+            pos = bnd + delta
+            pre = np.full(pos, 0x41, dtype=np.uint16)
+            for mid in ([0xD83D], [0xDE00], [0xDE00, 0xD83D], smile, [0x20AC], [0x0101] + smile):
+                data = np.concatenate([pre, np.array(mid, dtype=np.uint16), np.tile(smile, 700)]).astype(np.uint16)
+                check_utf16(G, orc, data, label=f"{bnd}{delta:+d} {mid}")
+
+
 # ---------------------------------------------------------------------------
 # random invalid inputs
 # ---------------------------------------------------------------------------
