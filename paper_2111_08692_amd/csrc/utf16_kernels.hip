@@ -450,18 +450,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     // a wave holding an unpaired surrogate; when an error before it is
     // already known, its output (past the valid prefix) is not written and
-    // its first error not located
-    bool lane_bad = false;
-    if (has_sur(cls)) {
-        if (kBatch) {
+    // its first error not located.  When converting, the check runs after
+    // the wave total is published (while wave 0 resolves the tile prefix),
+    // so it never delays the aggregate that later tiles wait for.
+    auto find_unpaired = [&]() -> bool {
+        bool lane_bad = false;
+        if (has_sur(cls)) {
+            if (kBatch) {
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) lane_bad |= unpaired_bits(t, r, lane, lane_starts16(bc, wbase, r, lane)) != 0;
-        } else {
-            lane_bad = lane_has_unpaired(t, lane);
+                for (int r = 0; r < kRows; ++r)
+                    lane_bad |= unpaired_bits(t, r, lane, lane_starts16(bc, wbase, r, lane)) != 0;
+            } else {
+                lane_bad = lane_has_unpaired(t, lane);
+            }
         }
-    }
-    const bool unpaired = has_sur(cls) && __ballot(lane_bad) != 0;
-    const bool moot = !kBatch && unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
+        return has_sur(cls) && __ballot(lane_bad) != 0;
+    };
+    bool unpaired = kConvert ? false : find_unpaired();
 
     if (kConvert) {
         uint32_t off[kRows], rowbase[kRows + 1];
@@ -501,7 +506,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 bc.blockoff[(wbase + r * kRowUnits + 8 * (long long)lane) >> 5] =
                     (uint16_t)(wave_off + rowbase[r] + off[r]);
         }
+        unpaired = find_unpaired();
         __syncthreads();   // the tile prefix is known
+        // an error before the wave is already known: its output lies past
+        // the valid prefix and is not written (the error word is read only
+        // now, off the path that publishes the tile's aggregate)
+        const bool moot = !kBatch && unpaired && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
         uint32_t *wst = stage + wave * kStageWords16;
         uint8_t *wst8 = (uint8_t *)wst;
         const u64 base = s_prefix + wave_off;
@@ -547,7 +557,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         return;
     }
     // the first unpaired surrogate, unless an error before the wave is known
-    if (unpaired && !moot && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
+    if (unpaired && (long long)(ld_agent(&ctrl->err) >> 4) >= wbase - head) {
         u64 err = lane_first_error16(t, wbase, head, end, lane);
         err = wave_min_u64(err);
         if (lane == 0 && err != ~0ull) min_agent(&ctrl->err, err);

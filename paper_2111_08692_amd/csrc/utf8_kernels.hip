@@ -1002,9 +1002,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         bool flag = sv.mis;
         fence_values(t);
         // a wave whose detector fired, when an error before it is already
-        // known: its output lies past the valid prefix and is not written
-        const bool moot =
-            !kBatch && kConvert && __ballot(flag) && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
+        // known: its output lies past the valid prefix and is not written.
+        // The error word is read after the tile prefix is known: read here,
+        // its latency would delay the tile's aggregate, which later tiles'
+        // look-back waits for.
+        const bool flagged = !kBatch && kConvert && __ballot(flag);
 
         if (kConvert) {
             // in-wave offsets (row-major) and wave total
@@ -1056,7 +1058,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
                 for (int g = 0; g < kRows / kGroup; ++g)
                     direct |= rowbase[(g + 1) * kGroup] - rowbase[g * kGroup] > kStageSlots;
-            if (!moot && !direct) switch (cls) {   // the first group needs no prefix
+            if (!direct) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
                 case kUpTo3: scatter_row<kUpTo3, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
                 case kQuad:   // staged after the prefix, except at the ends and in batches
@@ -1066,6 +1068,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
+            const bool moot = flagged && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
             if (direct) {
                 static_assert(kRows <= 4, "direct_words takes at most four rows");
                 u64 slot[4] = {0, 0, 0, 0};
