@@ -630,6 +630,23 @@ __device__ __forceinline__ uint32_t nibble_of(uint32_t m) {
     return (m | (m >> 7) | (m >> 14) | (m >> 21)) & 15u;
 }
 
+// Value rules of the leading bytes of every row (kQuad waves): run by
+// the waves that wait while wave 0 resolves the tile prefix, so their
+// staging after it skips them.
+__device__ __forceinline__ bool quad_values_bad(const LaneBytes &t, uint32_t lane) {
+    uint32_t bad = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t nx_row = next_dword(t, r, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = t.d[r][j], nx = j < 3 ? t.d[r][j + 1] : nx_row;
+            bad |= value_bits<kQuad>(x, __builtin_amdgcn_alignbyte(nx, x, 1));
+        }
+    }
+    return bad != 0;
+}
+
 // Stage the lane's chunk of row r (a wave away from the input's ends):
 // every position stores its first word at halfword o + slot and its low
 // surrogate one halfword further, in position order.  The last positions
@@ -637,7 +654,8 @@ __device__ __forceinline__ uint32_t nibble_of(uint32_t m) {
 // lane rewrites its own first two slots at the end: the first character's
 // first word, then its low surrogate or the second character's word.
 // Returns whether a value rule failed.
-__device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, uint32_t lane) {
+__device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, uint32_t lane,
+                                             bool vals) {
     uint16_t *st16 = (uint16_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
@@ -650,7 +668,7 @@ __device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t
         const uint32_t f0 = ge_f0(x) & 0x80808080u;
         uint32_t he, ho, le, lo;
         words4(x, nx, he, ho, le, lo);
-        bad |= value_bits<kQuad>(x, __builtin_amdgcn_alignbyte(nx, x, 1));
+        if (vals) bad |= value_bits<kQuad>(x, __builtin_amdgcn_alignbyte(nx, x, 1));
         if (j == 0) {
             h0e = he; h0o = ho; l0e = le; l0o = lo;
             L = nibble_of(lead);
@@ -792,7 +810,7 @@ template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
                                              const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
                                              u64 out_cap, uint32_t *wst, long long wbase, long long head,
-                                             long long end, uint32_t lane, bool staged0) {
+                                             long long end, uint32_t lane, bool staged0, bool vals = true) {
     bool bad = false;
     uintptr_t wlo = (uintptr_t)(out + (base < out_cap ? base : out_cap));   // lowest byte this wave writes
     uintptr_t gend = wlo;                                                  // end of the bytes done so far
@@ -816,7 +834,7 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
                 bad |= scatter_words<kClass, kFull>(t, r, h + gof[r], wst, wbase, head, end, lane);
         } else if (kClass == kQuad && !kFull && !t.edge) {
 #pragma unroll
-            for (int r = g * kGroup; r < (g + 1) * kGroup; ++r) bad |= scatter_quad(t, r, h + gof[r], wst, lane);
+            for (int r = g * kGroup; r < (g + 1) * kGroup; ++r) bad |= scatter_quad(t, r, h + gof[r], wst, lane, vals);
         } else {
             if (g > 0 || !staged0)
 #pragma unroll
@@ -1058,6 +1076,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
                 for (int g = 0; g < kRows / kGroup; ++g)
                     direct |= rowbase[(g + 1) * kGroup] - rowbase[g * kGroup] > kStageSlots;
+            // ASCII + four-byte waves stage only after the prefix: all waves
+            // but wave 0 check their value rules while it resolves it
+            const bool quad_pre = !kBatch && cls == kQuad && !t.edge && wave != 0;
+            if (quad_pre) flag |= quad_values_bad(t, lane);
             if (!direct) switch (cls) {   // the first group needs no prefix
                 case kAscii: break;
                 case kUpTo3: scatter_row<kUpTo3, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
@@ -1094,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     break;
                 case kQuad:
                     flag |= convert_wave<kQuad, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
-                                                true);
+                                                true, !quad_pre);
                     break;
                 default:
                     flag |= convert_wave<kAny, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
