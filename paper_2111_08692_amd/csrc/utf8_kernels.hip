@@ -438,6 +438,32 @@ __device__ __forceinline__ uint32_t decode_word(uint32_t w, bool &bad) {
     return l4 ? sur : u;
 }
 
+// Group 0 decoded before the tile prefix (and so h) is known, by the waves
+// that wait while wave 0 resolves it: each slot's word replaces its window.
+// `place_slots` then moves the words to halfword h + s, as decode_slots
+// would have stored them.
+template <uint32_t kClass>
+__device__ __forceinline__ bool decode_slots_early(uint32_t *wst, uint32_t nslots, uint32_t lane) {
+    bool bad = false;
+    for (uint32_t s = lane; s < nslots; s += kWave) wst[s] = decode_word<kClass>(wst[s], bad);
+    return bad;
+}
+
+__device__ __forceinline__ void place_slots(uint32_t *wst, uint32_t nslots, uint32_t h, uint32_t lane) {
+    constexpr int kU = 2;
+    uint16_t *w16 = (uint16_t *)wst;
+    for (uint32_t s0 = 0; s0 < nslots; s0 += kU * kWave) {
+        uint32_t w[kU];
+#pragma unroll
+        for (int i = 0; i < kU; ++i) {
+            const uint32_t s = s0 + i * kWave + lane;
+            w[i] = s < nslots ? wst[s] : 0x20u;   // the word decode_slots gives a slot past the group
+        }
+#pragma unroll
+        for (int i = 0; i < kU; ++i) w16[h + s0 + i * kWave + lane] = (uint16_t)w[i];
+    }
+}
+
 // Decode the group's slots [0, nslots) in place: slot s's word goes to
 // halfword h + s of the stage (lane-strided, so consecutive lanes touch
 // consecutive LDS banks).  A pass reads its windows before it writes, and
@@ -810,7 +836,8 @@ template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t (&gof)[kRows],
                                              const uint32_t (&rowbase)[kRows + 1], u64 base, uint16_t *out,
                                              u64 out_cap, uint32_t *wst, long long wbase, long long head,
-                                             long long end, uint32_t lane, bool staged0, bool vals = true) {
+                                             long long end, uint32_t lane, bool staged0, bool vals = true,
+                                             bool decoded0 = false) {
     bool bad = false;
     uintptr_t wlo = (uintptr_t)(out + (base < out_cap ? base : out_cap));   // lowest byte this wave writes
     uintptr_t gend = wlo;                                                  // end of the bytes done so far
@@ -841,7 +868,10 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
                 for (int r = g * kGroup; r < (g + 1) * kGroup; ++r)
                     scatter_row<kClass, kFull>(t, r, gof[r], wst, wbase, head, end, lane);
             wave_lds_sync();
-            bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
+            if (g == 0 && decoded0)
+                place_slots(wst, nslots, h, lane);
+            else
+                bad |= decode_slots<kClass>(wst, nslots, h, lane);   // value rules: even for rows not written
         }
         if (u0 < u1) {
             wave_lds_sync();
@@ -1088,6 +1118,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     break;
                 default: scatter_row<kAny, kBatch>(t, 0, gof[0], wst, wbase, head, end, lane); break;
             }
+            // windows classes: the waves waiting for wave 0 decode that group too
+            const bool early = !direct && (cls == kUpTo3 || cls == kAny) && wave != 0;
+            if (early) {
+                uint32_t n0 = rowbase[kGroup] - rowbase[0];
+                if (n0 > kStageSlots) n0 = kStageSlots;
+                wave_lds_sync();
+                flag |= cls == kUpTo3 ? decode_slots_early<kUpTo3>(wst, n0, lane) : decode_slots_early<kAny>(wst, n0, lane);
+            }
             __syncthreads();   // the tile prefix is known
             const u64 base = s_prefix + wave_off;
             const bool moot = flagged && (long long)(ld_agent(&ctrl->err) >> 4) < wbase - head;
@@ -1112,7 +1150,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     break;
                 case kUpTo3:
                     flag |= convert_wave<kUpTo3, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
-                                                 true);
+                                                 true, true, early);
                     break;
                 case kQuad:
                     flag |= convert_wave<kQuad, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
@@ -1120,7 +1158,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     break;
                 default:
                     flag |= convert_wave<kAny, kBatch>(t, gof, rowbase, base, out, out_cap, wst, wbase, head, end, lane,
-                                               true);
+                                               true, true, early);
                     break;
             }
         } else {
