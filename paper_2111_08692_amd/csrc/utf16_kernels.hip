@@ -19,8 +19,9 @@
 // Output.  A wave converts one row at a time into its LDS stage, laid out
 // by 16-byte blocks of the output (the row's first byte at stage byte
 // out & 15), then copies whole blocks out with aligned 16-byte stores.
-// Every word stores three bytes at its offset, in word order, so the bytes
-// past a shorter encoding are overwritten by the next word of the lane;
+// Every word stores three bytes at its offset (two in wave classes whose
+// words take at most two), in word order, so the bytes past a shorter
+// encoding are overwritten by the next word of the lane;
 // only the first two bytes of a lane can keep stray bytes (from the
 // previous lane's last word), and the lane rewrites them at the end.
 #include "device_common.hpp"
