@@ -144,6 +144,27 @@ def cpu_baseline(bufs, sample_bytes: int):
 # main
 # ---------------------------------------------------------------------------
 
+def copy_reference(dev, stream, aux):
+    """A plain 1 GiB device-to-device copy (the runtime's copy kernel): the
+    HBM rate a streaming kernel can practically reach on this device, for
+    reading the roofline fractions (bytes read + written per second)."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for s_, e_ in ev:
+        s_.record(stream)
+        b.copy_(a)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    t = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev) / 1e3
+    aux["d2d_copy_1gib_GBps"] = round(2 * (1 << 30) / t / 1e9, 1)
+    aux["d2d_copy_1gib_frac"] = round(2 * (1 << 30) / t / 1e9 / HBM_PEAK_GBS, 3)
+    del a, b
+
+
 def one_mib_latency(G, small, dev, stream, res, aux):
     """Latency of one synchronous 1 MiB call and the kernel time of one
     asynchronous call (the single-buffer 1 MiB case)."""
@@ -461,6 +482,7 @@ def main():
     # the 1 MiB single buffer: latency of one synchronous call
     if not args.no_aux:
         one_mib_latency(G, small, dev, stream, res, aux)
+        copy_reference(dev, stream, aux)
         log("batched strings")
         batch_leg(G, dev, stream, aux)
         log("serving")
