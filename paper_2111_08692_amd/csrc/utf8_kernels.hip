@@ -172,23 +172,14 @@ struct Survey {
 // bitmap bits (bit j for byte j).
 __device__ __forceinline__ uint32_t spread4(uint32_t b) { return ((b & 15u) * 0x10204080u) & 0x80808080u; }
 
-// Bitmap bits of string starts for the lane's chunk of each row: bits
-// 16..31 for the chunk's positions, bits 0..15 for the 16 positions before.
-struct StartBits {
-    uint32_t b[kRows];
-};
-
-// The start bits of each row's chunk and the 16 positions before it.  The
-// bitmap covers every tile of the call and 64 positions past them.
-__device__ __forceinline__ void load_start_bits(const BatchCtx &bc, long long wbase, uint32_t lane, StartBits &sb) {
-    const long long c0 = (wbase >> 4) + lane;   // chunk index of row 0
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const long long ci = c0 + r * (kRowBytes / 16);
-        const uint32_t cur = bc.starts[ci];
-        const uint32_t before = ci >= 1 ? (uint32_t)bc.starts[ci - 1] : 0u;
-        sb.b[r] = (cur << 16) | before;
-    }
+// Bitmap bits of string starts for the lane's chunk of row r: bits 16..31
+// for the chunk's positions, bits 0..15 for the 16 positions before.  The
+// bitmap covers every tile of the call and 64 positions past them.  Read
+// row by row as the survey reaches it (holding every row's bits from the
+// start of the kernel cost registers the batched kernel does not have).
+__device__ __forceinline__ uint32_t row_start_bits(const BatchCtx &bc, long long wbase, int r, uint32_t lane) {
+    const long long ci = (wbase >> 4) + lane + r * (kRowBytes / 16);   // chunk index
+    return ((uint32_t)bc.starts[ci] << 16) | (ci >= 1 ? (uint32_t)bc.starts[ci - 1] : 0u);
 }
 
 // With kBatch, a string start acts as a buffer end for the detector: a
@@ -196,7 +187,7 @@ __device__ __forceinline__ void load_start_bits(const BatchCtx &bc, long long wb
 // is flagged), and a continuation byte at it is covered by nothing.
 template <bool kBatch>
 __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase, long long head, long long end,
-                                            uint32_t lane, Survey &sv, const StartBits &sb) {
+                                            uint32_t lane, Survey &sv, const BatchCtx &bc) {
     uint32_t a80 = lane == 0 ? (t.hp & 0xFFFFFF00u) : 0u;
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
@@ -225,7 +216,8 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = prev_dword(t, r, lane);
         uint32_t pc0 = ge_c0(p), pe0 = ge_e0(p), pf0 = ge_f0(p);
-        uint32_t ps = kBatch ? spread4(sb.b[r] >> 12) : 0u;   // starts among the 4 positions before
+        const uint32_t sbr = kBatch ? row_start_bits(bc, wbase, r, lane) : 0u;
+        uint32_t ps = kBatch ? spread4(sbr >> 12) : 0u;   // starts among the 4 positions before
         uint32_t w = 16;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -237,7 +229,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
                            m3 = __builtin_amdgcn_alignbyte(f0, pf0, 1);
             const uint32_t cb = lane_cont_bits(t, r, k, wbase, head, end, lane);
             if (kBatch) {
-                const uint32_t s0 = spread4(sb.b[r] >> (16 + 4 * k));     // start at t
+                const uint32_t s0 = spread4(sbr >> (16 + 4 * k));     // start at t
                 const uint32_t s1 = __builtin_amdgcn_alignbyte(s0, ps, 3);  // start at t-1
                 const uint32_t s2 = __builtin_amdgcn_alignbyte(s0, ps, 2);  // start at t-2
                 const uint32_t x01 = s0 | s1, x012 = x01 | s2;
@@ -1037,14 +1029,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     LaneBytes t;
     issue_span(frame, end, wbase, lane, t);
     const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
-    // batched calls: string starts of each row's chunk and of the 16
-    // positions before it (the bitmap covers the whole frame and 64 past)
-    StartBits sb;
-    if (kBatch) load_start_bits(bc, wbase, lane, sb);
     finish_span(head, end, wbase, lane, t);
     {
         Survey sv;
-        survey_span<kBatch>(t, wbase, head, end, lane, sv, sb);
+        survey_span<kBatch>(t, wbase, head, end, lane, sv, bc);
         // the all-ASCII shortcut widens whole chunks: not for waves at the ends
         const uint32_t cls = (sv.cls == kAscii && t.edge) ? kUpTo2 : sv.cls;
         bool flag = sv.mis;
