@@ -423,6 +423,60 @@ __device__ __forceinline__ void narrow_row(const LaneUnits &t, int r, uint32_t s
     }
 }
 
+// All-ASCII waves away from the input's ends, with the whole wave's output
+// inside the capacity: each lane's eight bytes of a row go straight from
+// registers to memory.  With the wave's first output byte at g0 and
+// s8 = g0 & 7 (wave-uniform), lane-row q = 64 r + L holds wave bytes
+// [8q, 8q + 8) and stores the aligned 8-byte block at g0 - s8 + 8q, which
+// holds wave bytes [8q - s8, 8q - s8 + 8): the last s8 bytes of lane-row
+// q - 1 (the previous lane, or lane 63 of the previous row) and the first
+// 8 - s8 of its own.  The partial blocks at the wave's two ends take byte
+// stores, so no byte outside the wave's output is written.
+__device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g0p, uint32_t lane) {
+    const uintptr_t g0 = (uintptr_t)g0p;
+    const uint32_t s8 = (uint32_t)(g0 & 7u);
+    const uint32_t o = 8u - s8;   // the block's first byte in (previous lane-row, own lane-row)
+    uint32_t rlo = 0, rhi = 0;    // lane 63's bytes of the previous row
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t lo = __builtin_amdgcn_perm(t.d[r][1], t.d[r][0], 0x06040200u);
+        const uint32_t hi = __builtin_amdgcn_perm(t.d[r][3], t.d[r][2], 0x06040200u);
+        const uint32_t q = 64u * (uint32_t)r + lane;
+        if (s8 == 0) {
+            *(uint2 *)(g0 + 8u * q) = make_uint2(lo, hi);
+            continue;
+        }
+        uint32_t plo = __shfl_up(lo, 1), phi = __shfl_up(hi, 1);
+        if (lane == 0) {
+            plo = rlo;
+            phi = rhi;
+        }
+        rlo = readlane(lo, kWave - 1);
+        rhi = readlane(hi, kWave - 1);
+        uint32_t a, b;
+        if (o < 4u) {
+            a = __builtin_amdgcn_alignbyte(phi, plo, o);
+            b = __builtin_amdgcn_alignbyte(lo, phi, o);
+        } else {
+            a = __builtin_amdgcn_alignbyte(lo, phi, o - 4u);
+            b = __builtin_amdgcn_alignbyte(hi, lo, o - 4u);
+        }
+        if (q > 0) {
+            *(uint2 *)(g0 - s8 + 8u * q) = make_uint2(a, b);
+        } else {   // head: wave bytes [0, o)
+#pragma unroll
+            for (uint32_t i = 0; i < 7u; ++i)
+                if (i < o) ((uint8_t *)g0)[i] = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
+        }
+        if (r == kRows - 1 && lane == kWave - 1) {   // tail: own bytes [o, 8)
+#pragma unroll
+            for (uint32_t i = 1; i < 8u; ++i)
+                if (i >= o)
+                    ((uint8_t *)g0)[8u * q + i] = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
+        }
+    }
+}
+
 // Batched calls keep each 32-word block's output offset inside its tile in
 // 16 bits: a tile emits at most three bytes per word.
 static_assert(3 * kTileUnits <= 65536, "16-bit block offsets");
@@ -519,8 +573,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const uintptr_t wstart = (uintptr_t)(out + (base < out_cap ? base : out_cap));
         uintptr_t gend = wstart;   // end of the bytes written or carried so far
         Carry cy = {{0u, 0u, 0u, 0u}};
+        const bool direct = cls == kAscii16 && base + kWaveUnits <= out_cap;
+        if (direct) narrow_store_wave(t, out + base, lane);
 #pragma unroll
-        for (int r = 0; r < kRows && !moot; ++r) {
+        for (int r = 0; r < kRows && !moot && !direct; ++r) {
             const u64 b0 = base + rowbase[r];
             u64 b1 = base + rowbase[r + 1];
             if (b1 > out_cap) b1 = out_cap;
@@ -550,7 +606,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             gend = g1;
             wave_lds_sync();
         }
-        if (!moot) flush_carry<1>(gend, wstart, wst, cy, lane);
+        if (!moot && !direct) flush_carry<1>(gend, wstart, wst, cy, lane);
     }
 
     if (kBatch) {   // per string

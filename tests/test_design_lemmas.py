@@ -410,3 +410,50 @@ def test_surrogate_pair_bytes_split_by_word():
     text = "".join(map(chr, cp.tolist()))
     want = np.frombuffer(text.encode("utf-8"), dtype=np.uint8).reshape(-1, 4)
     assert np.array_equal(got, want)
+
+
+def _alignbyte(a, b, k):
+    """v_alignbyte_b32: bytes k..k+3 of the 8-byte value (a << 32 | b)."""
+    return ((a << 32 | b) >> (8 * k)) & 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("rows", [2, 4])
+def test_ascii_narrow_store_blocks(rows):
+    """Model of the UTF-16 -> UTF-8 all-ASCII direct store: for every
+    alignment of the wave's first output byte, the aligned 8-byte blocks of
+    lane-rows 1.. plus the head and tail byte stores write exactly the
+    wave's 512 * rows bytes, each once, with the right values."""
+    n = 512 * rows
+    rng = np.random.default_rng(rows)
+    wave = rng.integers(0, 128, size=n, dtype=np.uint64)
+    for base in range(8, 24):
+        s8 = base & 7
+        o = 8 - s8
+        mem = {}
+        lane_rows = [(int(sum(int(wave[8 * q + i]) << (8 * i) for i in range(4))),
+                      int(sum(int(wave[8 * q + 4 + i]) << (8 * i) for i in range(4)))) for q in range(n // 8)]
+        for q, (lo, hi) in enumerate(lane_rows):
+            def put(addr, byte):
+                assert addr not in mem, (base, q, addr)
+                mem[addr] = byte
+            if s8 == 0:
+                for i in range(8):
+                    put(base + 8 * q + i, ((lo | hi << 32) >> (8 * i)) & 0xFF)
+                continue
+            plo, phi = lane_rows[q - 1] if q > 0 else (0, 0)
+            if o < 4:
+                a, b = _alignbyte(phi, plo, o), _alignbyte(lo, phi, o)
+            else:
+                a, b = _alignbyte(lo, phi, o - 4), _alignbyte(hi, lo, o - 4)
+            if q > 0:
+                blk = a | b << 32
+                for i in range(8):
+                    put(base - s8 + 8 * q + i, (blk >> (8 * i)) & 0xFF)
+            else:
+                for i in range(o):
+                    put(base + i, ((lo | hi << 32) >> (8 * i)) & 0xFF)
+            if q == n // 8 - 1:
+                for i in range(o, 8):
+                    put(base + 8 * q + i, ((lo | hi << 32) >> (8 * i)) & 0xFF)
+        assert sorted(mem) == list(range(base, base + n)), base
+        assert all(mem[base + i] == int(wave[i]) for i in range(n)), base

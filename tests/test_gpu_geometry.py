@@ -167,3 +167,20 @@ def test_tuner_table_and_parity(G, orc, tmp_path):
             assert [names[G.get_geometry(T.OPS[op], c)] for c in range(G.SIZE_CLASSES)] == row
     finally:
         T.reset()
+
+
+def test_tuner_command_line(G, tmp_path):
+    """``python -m paper_2111_08692_amd.tune`` (its main(), in this process):
+    a file of text in, a JSON table out that installs again."""
+    from paper_2111_08692_amd import tune as T
+    text = tmp_path / "corpus.txt"
+    text.write_bytes(make_buffer("cyrillic", 300_000, seed=9).data.tobytes())
+    out = tmp_path / "t.json"
+    try:
+        assert T.main([str(text), "-o", str(out), "--ops", "convert_utf8_to_utf16le,validate_utf16le",
+                       "--sizes", "40000,400000"]) == 0
+        res = T.apply_file(str(out))
+        assert set(res["table"]) == {"convert_utf8_to_utf16le", "validate_utf16le"}
+        assert [r["bytes"] <= 400000 for r in res["measured"]["validate_utf16le"]] == [True, True]
+    finally:
+        T.reset()
