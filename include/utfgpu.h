@@ -228,7 +228,7 @@ int32_t utfgpu_release_workspace(void);
  * geometries: a workgroup of `waves` wave64 waves, each lane of which loads
  * `rows` 16-byte chunks, covers `tile_bytes` = waves * rows * 1024 input
  * bytes (UTF-8 bytes, or UTF-16LE bytes: half as many words).  Geometry 0
- * (8 waves x 4 rows, 32 KiB) is the default; smaller tiles put more
+ * (8 waves x 4 rows, 32 KiB) serves most calls; smaller tiles put more
  * workgroups on small inputs.  Every geometry computes the same results:
  * the choice only changes speed.
  *
@@ -236,7 +236,11 @@ int32_t utfgpu_release_workspace(void);
  * operation (UTF_OP_*) and input size class: the class of b input bytes is
  * ceil(log2(b)) (0 for b <= 1), clamped to UTF_SIZE_CLASSES - 1; UTF-16
  * inputs count 2 bytes per word and batched calls their whole input.  The
- * table starts at geometry 0 everywhere.  The environment variable
+ * table starts at the shipped defaults, measured on MI355X over text of five
+ * scripts: conversions of up to 4 MiB (class <= 22; batched UTF-8 calls up
+ * to 16 MiB) use 4 waves x 2 rows (8 KiB tiles), UTF-16LE -> UTF-8
+ * conversions above 64 MiB (class >= 27) 4 waves x 4 rows (16 KiB),
+ * everything else geometry 0.  The environment variable
  * UTFGPU_GEOMETRY, set to a geometry index before the first call, overrides
  * the table for the whole process.  The table is host state: these calls
  * need no GPU, may be made from any thread and take effect on the next
@@ -261,7 +265,7 @@ int32_t utfgpu_geometry_count(void);
 int32_t utfgpu_geometry(int32_t g, uint32_t *waves, uint32_t *rows, uint64_t *tile_bytes);
 
 /* Make calls of operation `op` whose input falls in `size_class` use
- * geometry g (-1 restores the default).  UTF_OK or UTF_ERR_ARG. */
+ * geometry g (-1 restores the shipped default).  UTF_OK or UTF_ERR_ARG. */
 int32_t utfgpu_set_geometry(int32_t op, int32_t size_class, int32_t g);
 
 /* The geometry such a call uses now (UTFGPU_GEOMETRY included), or
@@ -275,7 +279,7 @@ int32_t utfgpu_size_class(uint64_t bytes);
 const char *utfgpu_version(void);
 
 /* Input bytes one workgroup of the validate/convert kernels covers in the
- * default geometry (a tile of UTF-8 bytes, or of UTF-16LE bytes: half as
+ * geometry 0 (a tile of UTF-8 bytes, or of UTF-16LE bytes: half as
  * many words).  Informational: tests use it to place inputs across tile
  * boundaries.  Needs no GPU. */
 uint64_t utfgpu_tile_bytes(void);

@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -79,9 +80,39 @@ constexpr int kNumGeometries = (int)(sizeof(kGeometries) / sizeof(kGeometries[0]
 namespace base = utfgpu::g8x4;
 
 // Tuning table: per operation and input size class, 1 + the geometry index
-// (0: the default geometry).  Written by utfgpu_set_geometry, read once per
-// call; UTFGPU_GEOMETRY (an index) overrides it for the whole process.
+// (0: the shipped default below).  Written by utfgpu_set_geometry, read once
+// per call; UTFGPU_GEOMETRY (an index) overrides it for the whole process.
 std::atomic<uint8_t> g_table[UTF_OP_COUNT][UTF_SIZE_CLASSES];
+
+int geometry_index(const char *name) {
+    for (int i = 0; i < kNumGeometries; ++i)
+        if (std::strcmp(kGeometries[i].name, name) == 0) return i;
+    return 0;
+}
+
+// Shipped defaults, from timing every build on MI355X over the five script
+// mixes (ASCII, Latin, Cyrillic, CJK, emoji) and mixed-script text.
+// Conversions of up to 4 MiB (size class <= 22) run fastest in 8 KiB tiles:
+// 32 KiB tiles leave most CUs idle there.  UTF-16LE -> UTF-8 conversions of
+// more than 64 MiB (class >= 27) run in 16 KiB tiles: that kernel waits more
+// than it computes, and four workgroups per CU hide more of the waiting
+// (a loss on pure ASCII text, a gain on the other scripts).  Batched UTF-8
+// calls keep 8 KiB tiles up to 16 MiB.  Everything else: the 8 x 4 build.
+int shipped_geometry(int op, int c) {
+    static const int g4x2 = geometry_index("g4x2"), g4x4 = geometry_index("g4x4");
+    switch (op) {
+        case UTF_OP_CONVERT_UTF8: return c <= 22 ? g4x2 : 0;
+        case UTF_OP_CONVERT_UTF16LE:
+        case UTF_OP_BATCH_UTF16LE: return c <= 22 ? g4x2 : (c >= 27 ? g4x4 : 0);
+        case UTF_OP_BATCH_UTF8: return c <= 24 ? g4x2 : 0;
+        default: return 0;
+    }
+}
+
+int table_geometry(int op, int c) {
+    const int g = (int)g_table[op][c].load(std::memory_order_relaxed) - 1;
+    return g >= 0 && g < kNumGeometries ? g : shipped_geometry(op, c);
+}
 
 int forced_geometry() {
     static const int g = [] {
@@ -101,8 +132,7 @@ int size_class(u64 bytes) {
 const Geometry &geometry_for(int op, u64 bytes) {
     const int f = forced_geometry();
     if (f >= 0) return kGeometries[f];
-    const int g = (int)g_table[op][size_class(bytes)].load(std::memory_order_relaxed) - 1;
-    return kGeometries[g > 0 && g < kNumGeometries ? g : 0];
+    return kGeometries[table_geometry(op, size_class(bytes))];
 }
 
 }  // namespace
@@ -584,8 +614,7 @@ int32_t utfgpu_get_geometry(int32_t op, int32_t size_class) {
     if (op < 0 || op >= UTF_OP_COUNT || size_class < 0 || size_class >= UTF_SIZE_CLASSES) return UTF_ERR_ARG;
     const int f = forced_geometry();
     if (f >= 0) return f;
-    const int g = (int)g_table[op][size_class].load(std::memory_order_relaxed) - 1;
-    return g > 0 && g < kNumGeometries ? g : 0;
+    return table_geometry(op, size_class);
 }
 
 int32_t utfgpu_size_class(uint64_t bytes) { return size_class(bytes); }

@@ -9,9 +9,10 @@ tiles put more workgroups on small inputs.
 
 ``tune`` times every geometry on the caller's representative text at a ladder
 of input sizes, for each operation asked for, with HIP events on the current
-stream.  A measured class keeps the default geometry unless another is faster
-by more than ``min_gain``; every other class takes the choice of the nearest
-measured class.  The result is installed and returned as a JSON-ready dict;
+stream.  A measured class keeps the geometry it had (the library's shipped
+default, unless a table was installed) unless another is faster by more than
+``min_gain``; every other class takes the choice of the nearest measured
+class.  The result is installed and returned as a JSON-ready dict;
 ``save`` and ``apply_file`` keep it in a JSON cache that records the library
 version and the geometry list, so a cache from another build is refused.
 
@@ -54,7 +55,7 @@ def geometry_names() -> List[str]:
 def nearest_fill(measured: Dict[int, int], nclasses: int = SIZE_CLASSES) -> List[int]:
     """Table row over every size class from the choices at the measured
     classes: each class takes the choice of the nearest measured class (the
-    smaller one on a tie); no measurement leaves the default (-1)."""
+    smaller one on a tie); no measurement leaves every class as it is (-1)."""
     if not measured:
         return [-1] * nclasses
     keys = sorted(measured)
@@ -65,12 +66,12 @@ def nearest_fill(measured: Dict[int, int], nclasses: int = SIZE_CLASSES) -> List
     return row
 
 
-def choose(times_us: Sequence[float], min_gain: float) -> int:
+def choose(times_us: Sequence[float], min_gain: float, current: int = 0) -> int:
     """Index of the geometry to use given per-geometry times: the fastest,
-    unless it beats the default (index 0) by ``min_gain`` or less (-1)."""
+    unless it beats the ``current`` one by ``min_gain`` or less."""
     best = int(np.argmin(times_us))
-    if best == 0 or times_us[best] * (1.0 + min_gain) >= times_us[0]:
-        return -1
+    if best == current or times_us[best] * (1.0 + min_gain) >= times_us[current]:
+        return current
     return best
 
 
@@ -207,7 +208,8 @@ def tune(sample: np.ndarray, ops: Sequence[str] = tuple(OPS), sizes: Sequence[in
     inputs = _Inputs(sample, max(sizes), dev)
     measured: Dict[str, list] = {}
     table: Dict[str, List[int]] = {}
-    saved = {op: [get_geometry(OPS[op], c) for c in range(SIZE_CLASSES)] for op in ops}
+    saved_all = {op: [get_geometry(OPS[op], c) for c in range(SIZE_CLASSES)] for op in OPS}
+    saved = {op: saved_all[op] for op in ops}
     try:
         for name in ops:
             op = OPS[name]
@@ -219,27 +221,28 @@ def tune(sample: np.ndarray, ops: Sequence[str] = tuple(OPS), sizes: Sequence[in
                 real = data.numel() * data.element_size()
                 c = size_class(real)
                 fn = _call(op, data, string_bytes)
+                current = saved_all[name][c]
                 times = []
                 for g in range(len(names)):
                     _ok(set_geometry(op, c, g))
                     if get_geometry(op, c) != g:
                         raise RuntimeError("UTFGPU_GEOMETRY is set: the geometry cannot be tuned")
                     times.append(_time_us(fn, min_ms, reps))
-                pick = choose(times, min_gain)
+                pick = choose(times, min_gain, current)
                 choices[c] = pick
                 rows.append({"bytes": real, "class": c, "us": [round(t, 3) for t in times],
-                             "choice": names[pick] if pick >= 0 else names[0]})
+                             "before": names[current], "choice": names[pick]})
                 del fn, data
             measured[name] = rows
-            table[name] = nearest_fill(choices)
+            table[name] = [g if g >= 0 else saved_all[name][c] for c, g in enumerate(nearest_fill(choices))]
     finally:
         for name, row in saved.items():   # restore, then install the result
             for c, g in enumerate(row):
-                set_geometry(OPS[name], c, g if g != 0 else -1)
+                set_geometry(OPS[name], c, g)
         torch.cuda.synchronize()
     result = {"library": version(), "geometries": names, "min_gain": min_gain, "string_bytes": string_bytes,
               "measured": measured,
-              "table": {op: [names[g] if g >= 0 else names[0] for g in row] for op, row in table.items()}}
+              "table": {op: [names[g] for g in row] for op, row in table.items()}}
     if install:
         apply(result)
     return result
@@ -262,12 +265,11 @@ def apply(result: dict) -> None:
             raise ValueError(f"{op}: unknown geometries {sorted(unknown)}")
     for op, row in result["table"].items():
         for c, gname in enumerate(row):
-            g = names.index(gname)
-            _ok(set_geometry(OPS[op], c, g if g != 0 else -1))
+            _ok(set_geometry(OPS[op], c, names.index(gname)))
 
 
 def reset() -> None:
-    """Every operation and class back to the default geometry."""
+    """Every operation and class back to the library's shipped default."""
     for op in OPS.values():
         for c in range(SIZE_CLASSES):
             _ok(set_geometry(op, c, -1))

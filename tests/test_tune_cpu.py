@@ -45,15 +45,35 @@ def test_size_class_is_ceil_log2(G):
     assert G.size_class((1 << 64) - 1) == G.SIZE_CLASSES - 1
 
 
+def test_shipped_defaults(G):
+    names = [f"{w}x{r}" for w, r, _ in G.geometries()]
+    g0, g4x2, g4x4 = 0, names.index("4x2"), names.index("4x4")
+    for op in range(G.OP_COUNT):
+        for c in range(G.SIZE_CLASSES):
+            G.set_geometry(op, c, -1)
+    want = {
+        G.OP_VALIDATE_UTF8: lambda c: g0,
+        G.OP_VALIDATE_UTF16LE: lambda c: g0,
+        G.OP_CONVERT_UTF8: lambda c: g4x2 if c <= 22 else g0,
+        G.OP_CONVERT_UTF16LE: lambda c: g4x2 if c <= 22 else (g4x4 if c >= 27 else g0),
+        G.OP_BATCH_UTF16LE: lambda c: g4x2 if c <= 22 else (g4x4 if c >= 27 else g0),
+        G.OP_BATCH_UTF8: lambda c: g4x2 if c <= 24 else g0,
+    }
+    for op, f in want.items():
+        assert [G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] == [f(c) for c in range(G.SIZE_CLASSES)], op
+
+
 def test_set_get_and_argument_checks(G):
     ng = len(G.geometries())
-    assert G.get_geometry(G.OP_CONVERT_UTF8, 20) == 0
-    assert G.set_geometry(G.OP_CONVERT_UTF8, 20, ng - 1) == G.OK
-    assert G.get_geometry(G.OP_CONVERT_UTF8, 20) == ng - 1
+    shipped20 = G.get_geometry(G.OP_CONVERT_UTF8, 20)
+    shipped21 = G.get_geometry(G.OP_CONVERT_UTF8, 21)
+    other = (shipped20 + 1) % ng
+    assert G.set_geometry(G.OP_CONVERT_UTF8, 20, other) == G.OK
+    assert G.get_geometry(G.OP_CONVERT_UTF8, 20) == other
     # other operations and classes are untouched
-    assert G.get_geometry(G.OP_CONVERT_UTF8, 21) == 0 and G.get_geometry(G.OP_VALIDATE_UTF8, 20) == 0
+    assert G.get_geometry(G.OP_CONVERT_UTF8, 21) == shipped21 and G.get_geometry(G.OP_VALIDATE_UTF8, 20) == 0
     assert G.set_geometry(G.OP_CONVERT_UTF8, 20, -1) == G.OK
-    assert G.get_geometry(G.OP_CONVERT_UTF8, 20) == 0
+    assert G.get_geometry(G.OP_CONVERT_UTF8, 20) == shipped20
     for op, c, g in ((-1, 0, 0), (G.OP_COUNT, 0, 0), (0, -1, 0), (0, G.SIZE_CLASSES, 0), (0, 0, ng), (0, 0, -2)):
         assert G.set_geometry(op, c, g) == G.ERR_ARG, (op, c, g)
     assert G.get_geometry(G.OP_COUNT, 0) == G.ERR_ARG and G.get_geometry(0, G.SIZE_CLASSES) == G.ERR_ARG
@@ -62,8 +82,10 @@ def test_set_get_and_argument_checks(G):
 
 def test_choose_and_fill(T):
     assert T.choose([10.0, 9.0, 11.0], 0.03) == 1
-    assert T.choose([10.0, 9.8, 11.0], 0.03) == -1   # within the margin: the default stays
-    assert T.choose([10.0, 10.5, 11.0], 0.0) == -1
+    assert T.choose([10.0, 9.8, 11.0], 0.03) == 0   # within the margin: the current geometry stays
+    assert T.choose([10.0, 10.5, 11.0], 0.0) == 0
+    assert T.choose([10.0, 9.0, 8.9], 0.03, current=2) == 2
+    assert T.choose([8.0, 9.0, 8.9], 0.03, current=2) == 0
     row = T.nearest_fill({16: 2, 20: -1, 24: 1}, 30)
     assert row[:19] == [2] * 19 and row[19:23] == [-1] * 4 and row[23:] == [1] * 7
     assert row[18] == 2 and row[22] == -1   # ties go to the smaller class
@@ -98,6 +120,8 @@ def _table(T, G, pick):
 
 
 def test_apply_save_load_reset(T, G, tmp_path):
+    T.reset()
+    shipped = [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)]
     res = _table(T, G, lambda i, c: i + c)
     path = tmp_path / "t.json"
     T.save(res, str(path))
@@ -107,7 +131,7 @@ def test_apply_save_load_reset(T, G, tmp_path):
         for c in range(G.SIZE_CLASSES):
             assert G.get_geometry(T.OPS[op], c) == (i + c) % n
     T.reset()
-    assert all(G.get_geometry(op, c) == 0 for op in range(G.OP_COUNT) for c in range(G.SIZE_CLASSES))
+    assert [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)] == shipped
 
 
 def test_apply_refuses_a_foreign_table(T, G, tmp_path):
