@@ -515,8 +515,7 @@ def main():
                                "validating",
                    "buffers_per_step": len(bufs), "input_bytes_per_step": in_bytes,
                    "buffer_bytes": size,
-                   "tile_geometry": "shipped table: 8 waves x 4 rows (32 KiB tiles) for UTF-8->UTF-16LE, "
-                                    "4 waves x 4 rows (16 KiB tiles) for UTF-16LE->UTF-8 at 1 GiB",
+                   "tile_geometry": "shipped table: 8 waves x 4 rows (32 KiB tiles) at 1 GiB, both directions",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

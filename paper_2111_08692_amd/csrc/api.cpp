@@ -93,17 +93,15 @@ int geometry_index(const char *name) {
 // Shipped defaults, from timing every build on MI355X over the five script
 // mixes (ASCII, Latin, Cyrillic, CJK, emoji) and mixed-script text.
 // Conversions of up to 4 MiB (size class <= 22) run fastest in 8 KiB tiles:
-// 32 KiB tiles leave most CUs idle there.  UTF-16LE -> UTF-8 conversions of
-// more than 64 MiB (class >= 27) run in 16 KiB tiles: that kernel waits more
-// than it computes, and four workgroups per CU hide more of the waiting
-// (a loss on pure ASCII text, a gain on the other scripts).  Batched UTF-8
-// calls keep 8 KiB tiles up to 16 MiB.  Everything else: the 8 x 4 build.
+// 32 KiB tiles leave most CUs idle there.  Batched UTF-8 calls keep 8 KiB
+// tiles up to 16 MiB.  Everything else: the 8 x 4 build (16 KiB tiles win
+// on non-ASCII text and lose more on ASCII).
 int shipped_geometry(int op, int c) {
-    static const int g4x2 = geometry_index("g4x2"), g4x4 = geometry_index("g4x4");
+    static const int g4x2 = geometry_index("g4x2");
     switch (op) {
-        case UTF_OP_CONVERT_UTF8: return c <= 22 ? g4x2 : 0;
+        case UTF_OP_CONVERT_UTF8:
         case UTF_OP_CONVERT_UTF16LE:
-        case UTF_OP_BATCH_UTF16LE: return c <= 22 ? g4x2 : (c >= 27 ? g4x4 : 0);
+        case UTF_OP_BATCH_UTF16LE: return c <= 22 ? g4x2 : 0;
         case UTF_OP_BATCH_UTF8: return c <= 24 ? g4x2 : 0;
         default: return 0;
     }
