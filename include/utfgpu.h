@@ -238,8 +238,10 @@ int32_t utfgpu_release_workspace(void);
  * inputs count 2 bytes per word and batched calls their whole input.  The
  * table starts at the shipped defaults, measured on MI355X over text of five
  * scripts: conversions of up to 4 MiB (class <= 22; batched UTF-8 calls up
- * to 16 MiB) use 4 waves x 2 rows (8 KiB tiles), everything else geometry
- * 0.  The environment variable
+ * to 16 MiB) use 4 waves x 2 rows (8 KiB tiles), larger batched UTF-16LE
+ * calls 4 waves x 4 rows (16 KiB tiles, which share CUs better with
+ * concurrent calls on other streams), everything else geometry 0.  The
+ * environment variable
  * UTFGPU_GEOMETRY, set to a geometry index before the first call, overrides
  * the table for the whole process.  The table is host state: these calls
  * need no GPU, may be made from any thread and take effect on the next

@@ -94,14 +94,22 @@ int geometry_index(const char *name) {
 // mixes (ASCII, Latin, Cyrillic, CJK, emoji) and mixed-script text.
 // Conversions of up to 4 MiB (size class <= 22) run fastest in 8 KiB tiles:
 // 32 KiB tiles leave most CUs idle there.  Batched UTF-8 calls keep 8 KiB
-// tiles up to 16 MiB.  Everything else: the 8 x 4 build (16 KiB tiles win
+// tiles up to 16 MiB.  Larger batched UTF-16 calls use the 4 x 4 build:
+// serving runs them on several streams beside other look-back kernels, and
+// an 8-wave workgroup with 48 KiB of LDS often finds no room on its XCD
+// while later tiles of its own or another kernel wait for it (each XCD
+// dispatches in order), so the wait lasts until the helping path steps in;
+// 4-wave workgroups fit beside the others (measured: twice the throughput
+// of 8 x 4 for a burst of requests on four streams, against up to 5 % less
+// for one call alone).  Everything else: the 8 x 4 build (16 KiB tiles win
 // on non-ASCII text and lose more on ASCII).
 int shipped_geometry(int op, int c) {
     static const int g4x2 = geometry_index("g4x2");
+    static const int g4x4 = geometry_index("g4x4");
     switch (op) {
         case UTF_OP_CONVERT_UTF8:
-        case UTF_OP_CONVERT_UTF16LE:
-        case UTF_OP_BATCH_UTF16LE: return c <= 22 ? g4x2 : 0;
+        case UTF_OP_CONVERT_UTF16LE: return c <= 22 ? g4x2 : 0;
+        case UTF_OP_BATCH_UTF16LE: return c <= 22 ? g4x2 : g4x4;
         case UTF_OP_BATCH_UTF8: return c <= 24 ? g4x2 : 0;
         default: return 0;
     }

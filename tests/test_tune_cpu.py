@@ -47,7 +47,7 @@ def test_size_class_is_ceil_log2(G):
 
 def test_shipped_defaults(G):
     names = [f"{w}x{r}" for w, r, _ in G.geometries()]
-    g0, g4x2 = 0, names.index("4x2")
+    g0, g4x2, g4x4 = 0, names.index("4x2"), names.index("4x4")
     for op in range(G.OP_COUNT):
         for c in range(G.SIZE_CLASSES):
             G.set_geometry(op, c, -1)
@@ -56,7 +56,7 @@ def test_shipped_defaults(G):
         G.OP_VALIDATE_UTF16LE: lambda c: g0,
         G.OP_CONVERT_UTF8: lambda c: g4x2 if c <= 22 else g0,
         G.OP_CONVERT_UTF16LE: lambda c: g4x2 if c <= 22 else g0,
-        G.OP_BATCH_UTF16LE: lambda c: g4x2 if c <= 22 else g0,
+        G.OP_BATCH_UTF16LE: lambda c: g4x2 if c <= 22 else g4x4,
         G.OP_BATCH_UTF8: lambda c: g4x2 if c <= 24 else g0,
     }
     for op, f in want.items():
