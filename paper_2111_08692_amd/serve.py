@@ -90,6 +90,30 @@ class _Ring:
         self.used -= nbytes
 
 
+def prewarm_windows(off: np.ndarray, kind: int, max_batch_bytes: int, pool_bytes: int) -> List[Tuple[int, int]]:
+    """Queue windows [i, j) of one direction (``off``: its requests' unit
+    offsets) with the most input units and with the most requests among
+    the batches ``Server.run`` can form when every request has arrived:
+    from any i, up to the batch limit in input bytes, at least one request,
+    and an output reservation (4 bytes per UTF-8 byte, 3 per UTF-16LE unit)
+    that fits the pool."""
+    nq = int(off.size) - 1
+    if nq <= 0:
+        return []
+    per_unit = 4 if kind == 0 else 3
+    i = np.arange(nq)
+    j = np.maximum(np.searchsorted(off, off[:-1] + max_batch_bytes // (1 + kind), side="right") - 1, i + 1)
+    # a reservation that does not fit the pool is admitted shorter
+    fit = np.searchsorted(off, off[:-1] + pool_bytes // per_unit, side="right") - 1
+    j = np.where(per_unit * (off[j] - off[i]) <= pool_bytes, j, np.maximum(np.minimum(j, fit), i + 1))
+    units = off[j] - off[i]
+    ok = per_unit * units <= pool_bytes
+    if not ok.any():
+        return []
+    picks = {int(np.argmax(np.where(ok, units, -1))), int(np.argmax(np.where(ok, j - i, -1)))}
+    return [(a, int(j[a])) for a in sorted(picks)]
+
+
 class Server:
     """Device-resident payload arenas, per-direction output pools and a
     stream pool.  ``reqs`` is a ``workloads.RequestSet``."""
@@ -115,6 +139,46 @@ class Server:
         self.res8_host = torch.zeros((max(n8, 1), 2), dtype=torch.int64).pin_memory()
         self.res16_host = torch.zeros((max(n16, 1), 2), dtype=torch.int64).pin_memory()
         torch.cuda.synchronize()
+
+    def _launch(self, kind: int, i: int, j: int, start: int, s: torch.cuda.Stream):
+        """One batched call on stream ``s`` over positions i..j-1 of the
+        queue of direction ``kind`` (0: UTF-8 -> UTF-16LE), output from byte
+        ``start`` of that direction's pool; returns the device output
+        offsets and results."""
+        off_k, off_dev = (self.r.off8, self.off8_dev) if kind == 0 else (self.r.off16, self.off16_dev)
+        k, nu = j - i, int(off_k[j] - off_k[i])
+        with torch.cuda.stream(s):
+            offs = off_dev[i:j + 1] - int(off_k[i])
+            oo = torch.empty(k + 1, dtype=torch.int64, device=self.dev)
+            res = results_tensor(k, device=self.dev)
+            if kind == 0:
+                out = self.out16[start // 2:start // 2 + 2 * nu] if nu else self.out16[:1]
+                rc = convert_utf8_to_utf16le_batch_async(self.d8[int(off_k[i]):int(off_k[j])], offs, out,
+                                                         oo, res, out_cap=2 * nu, stream=s)
+            else:
+                out = self.out8[start:start + 3 * nu] if nu else self.out8[:1]
+                rc = convert_utf16le_to_utf8_batch_async(self.d16[int(off_k[i]):int(off_k[j])], offs, out,
+                                                         oo, res, out_cap=3 * nu, stream=s)
+        if rc != 0:
+            raise RuntimeError(f"batched call failed: {rc}")
+        return oo, res
+
+    def prewarm(self) -> None:
+        """Bring every stream's library workspace to the size the largest
+        batch of this request set needs, so that no call made while requests
+        are served has to grow one (growing drains the stream and frees
+        device memory, which waits for the whole device).  Per direction
+        and stream, one batched call over the window of queued requests
+        with the most input and one over the window with the most requests,
+        each as long as ``run`` may form a batch (the batch limit and the
+        output pool).  Run it again after changing the geometry table."""
+        r = self.r
+        for kind, off in ((0, r.off8), (1, r.off16)):
+            wins = prewarm_windows(off, kind, self.max_batch_bytes, self.pool_bytes)
+            for s in self.streams:
+                for i, j in wins:
+                    self._launch(kind, i, j, 0, s)
+                s.synchronize()   # the calls share the pool's first bytes
 
     def run(self, time_scale: float = 1.0) -> ServeResult:
         """Serve every request once, replaying arrivals in wall-clock time
@@ -159,23 +223,11 @@ class Server:
                 if got is None:
                     continue
                 start, held = got
-                k, nu = j - i, int(off_k[j] - off_k[i])
+                k = j - i
                 s = self.streams[si % len(self.streams)]
                 si += 1
                 with torch.cuda.stream(s):
-                    offs = q["off_dev"][i:j + 1] - int(off_k[i])
-                    oo = torch.empty(k + 1, dtype=torch.int64, device=self.dev)
-                    res = results_tensor(k, device=self.dev)
-                    if kind == 0:
-                        out = self.out16[start // 2:start // 2 + 2 * nu] if nu else self.out16[:1]
-                        rc = convert_utf8_to_utf16le_batch_async(self.d8[int(off_k[i]):int(off_k[j])], offs, out,
-                                                                 oo, res, out_cap=2 * nu, stream=s)
-                    else:
-                        out = self.out8[start:start + 3 * nu] if nu else self.out8[:1]
-                        rc = convert_utf16le_to_utf8_batch_async(self.d16[int(off_k[i]):int(off_k[j])], offs, out,
-                                                                 oo, res, out_cap=3 * nu, stream=s)
-                    if rc != 0:
-                        raise RuntimeError(f"batched call failed: {rc}")
+                    oo, res = self._launch(kind, i, j, start, s)
                     q["host"][i:j].copy_(res[:k], non_blocking=True)
                     ev = torch.cuda.Event()
                     ev.record(s)

@@ -26,6 +26,7 @@ def served(G):
                          pool_bytes=4 << 20)
     bound = max(4 * reqs.data8.size, 3 * reqs.data16.size) + (1 << 20)
     srv = Server(reqs, nstreams=3, pool_bytes=bound, max_batch_bytes=1 << 20)
+    srv.prewarm()
     res = srv.run()
     return reqs, srv, res
 

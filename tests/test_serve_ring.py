@@ -1,7 +1,9 @@
-"""Host logic of the serving loop: the output-pool ring (no GPU)."""
+"""Host logic of the serving loop: the output-pool ring and the windows
+that pre-size the library's workspaces (no GPU)."""
+import numpy as np
 import pytest
 
-from paper_2111_08692_amd.serve import _Ring
+from paper_2111_08692_amd.serve import _Ring, prewarm_windows
 
 
 def test_ring_alloc_free_wrap():
@@ -21,3 +23,41 @@ def test_ring_alloc_free_wrap():
 def test_ring_rejects_oversize():
     with pytest.raises(ValueError):
         _Ring(10).alloc(11)
+
+
+def _formable(off, kind, max_batch, pool):
+    """Every batch the scheduler can form with all requests arrived: from
+    each i, the window up to the batch limit, halved while its output
+    reservation exceeds the pool (as the scheduler does for a full ring)."""
+    per_unit = 4 if kind == 0 else 3
+    nq = off.size - 1
+    for i in range(nq):
+        j = max(int(np.searchsorted(off, off[i] + max_batch // (1 + kind), side="right")) - 1, i + 1)
+        while True:
+            if per_unit * int(off[j] - off[i]) <= pool:
+                yield i, j
+            if j == i + 1:
+                break
+            j = i + (j - i) // 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_prewarm_windows_bound_every_batch(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    sizes = np.exp(rng.normal(np.log(200), 1.5, size=n)).astype(np.int64) + 1
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for kind in (0, 1):
+        max_batch = int(rng.integers(50, 20_000))
+        pool = int(rng.integers(100, 40_000))
+        wins = prewarm_windows(off, kind, max_batch, pool)
+        per_unit = 4 if kind == 0 else 3
+        formable = list(_formable(off, kind, max_batch, pool))
+        if not formable:
+            assert wins == []
+            continue
+        assert 1 <= len(wins) <= 2
+        for i, j in wins:   # each is a call the pool can hold
+            assert 0 <= i < j <= n and per_unit * int(off[j] - off[i]) <= pool
+        assert max(int(off[j] - off[i]) for i, j in wins) >= max(int(off[j] - off[i]) for i, j in formable)
+        assert max(j - i for i, j in wins) >= max(j - i for i, j in formable)
