@@ -314,7 +314,7 @@ def host_leg(bufs, aux):
         if mix != "cjk" or kind != "valid":
             continue
         conv = p.convert_utf8_to_utf16le if enc == "utf-8" else p.convert_utf16le_to_utf8
-        conv(b.data[: (64 << 20) // b.data.itemsize])   # warm-up
+        conv(b.data[: 3 * (64 << 20) // b.data.itemsize])   # warm-up: one chunk on each stream
         st, cnt, out = conv(b.data)
         assert st == 0
         d = "8to16" if enc == "utf-8" else "16to8"
