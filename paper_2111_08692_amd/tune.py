@@ -12,7 +12,12 @@ of input sizes, for each operation asked for, with HIP events on the current
 stream.  A measured class keeps the geometry it had (the library's shipped
 default, unless a table was installed) unless another is faster by more than
 ``min_gain``; every other class takes the choice of the nearest measured
-class.  The result is installed and returned as a JSON-ready dict;
+class.  Calls are timed one at a time on one stream: a geometry that wins
+there can lose when calls run concurrently on several streams (the shipped
+table keeps 16 KiB tiles for large batched UTF-16LE calls for that reason),
+so a server that overlaps calls should leave those classes out of the
+tuned operations or check the tuned table under its own load.  The result
+is installed and returned as a JSON-ready dict;
 ``save`` and ``apply_file`` keep it in a JSON cache that records the library
 version and the geometry list, so a cache from another build is refused.
 
