@@ -16,8 +16,9 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.test_oracle_pins import (EDGE8, N8, _all_scalars, _fixture, cpy_utf8, cpy_utf16,
-                                    error_histogram)
+from tests.test_oracle_pins import (EDGE8, N8, _all_scalars, _edit16, _fixture, _units8_of_utf16,
+                                    _units16_of_utf8, cpy_utf8, cpy_utf16, error_histogram)
+from workloads import random_text
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "utf_oracle.c")
 NAMES = {v: k for k, v in O.STATUS_NAMES.items()}
@@ -60,6 +61,13 @@ MUTANTS = [
     ("length: surrogate words", "else if (w >= 0xD800 && w <= 0xDFFF)\n            bytes += 2;", "else if (w >= 0xD800 && w <= 0xDFFF)\n            bytes += 3;"),
     ("capacity test", "if (o > cap) {", "if (o >= cap) {"),
     ("word assembly", "((uint32_t)s[2 * i + 1] << 8)", "((uint32_t)s[2 * i + 1] << 7)"),
+    # batched forms (each keeps every write inside the output the wrapper sizes)
+    ("utf-8 batch output offsets", "out + 2 * o, room);\n        o += (int64_t)room;",
+     "out + 2 * o, room);\n        o += (int64_t)(room ? room - 1 : 0);"),
+    ("utf-16 batch output offsets", "out + o, room);\n        o += (int64_t)room;",
+     "out + o, room);\n        o += (int64_t)len;"),
+    ("utf-16 batch reported offset", "out_offsets[j] = o;\n        results[j] = oracle_convert_utf16le_to_utf8",
+     "out_offsets[j] = o + (j > 0);\n        results[j] = oracle_convert_utf16le_to_utf8"),
 ]
 
 
@@ -149,7 +157,40 @@ def battery(lib) -> list:
     check("golden", golden)
     check("cpython utf-8", cpython8)
     check("cpython utf-16", cpython16)
+    def batches():
+        rng = np.random.default_rng(16)
+        for _ in range(20):
+            k = int(rng.integers(1, 30))
+            s8 = [random_text(rng, "mix1m", int(rng.integers(0, 20))).tobytes() for _ in range(k)]
+            s16 = []
+            for x in s8:
+                w = np.frombuffer(x.decode("utf-8").encode("utf-16-le"), dtype="<u2").astype(np.uint16)
+                s16.append(np.array(_edit16(rng, w), dtype=np.uint16) if w.size and rng.random() < 0.3 else w)
+            data = np.frombuffer(b"".join(s8) + b"\0", dtype=np.uint8)[:sum(map(len, s8))]
+            off = np.concatenate([[0], np.cumsum([len(x) for x in s8])]).astype(np.int64)
+            st, cnt, out, oo = O.convert_utf8_to_utf16le_batch(data, off, lib=lib)
+            if not np.array_equal(oo, np.concatenate([[0], np.cumsum([_units16_of_utf8(x) for x in s8])])):
+                return False
+            for i, x in enumerate(s8):
+                ref = np.frombuffer(x.decode("utf-8").encode("utf-16-le"), dtype="<u2")
+                if st[i] != 0 or cnt[i] != ref.size or not np.array_equal(out[oo[i]:oo[i] + ref.size], ref):
+                    return False
+            d16 = np.concatenate(s16 + [np.zeros(1, np.uint16)])[:sum(x.size for x in s16)]
+            off16 = np.concatenate([[0], np.cumsum([x.size for x in s16])]).astype(np.int64)
+            st, cnt, out, oo = O.convert_utf16le_to_utf8_batch(d16, off16, lib=lib)
+            if not np.array_equal(oo, np.concatenate([[0], np.cumsum([_units8_of_utf16(x) for x in s16])])):
+                return False
+            for i, x in enumerate(s16):
+                kind, pos, txt = cpy_utf16(x.astype("<u2").tobytes())
+                if (st[i], cnt[i]) != ((0, len(txt.encode("utf-8"))) if kind == 0 else (kind, pos)):
+                    return False
+                ref = np.frombuffer(txt.encode("utf-8"), dtype=np.uint8) if kind == 0 else None
+                if ref is not None and not np.array_equal(out[oo[i]:oo[i] + ref.size], ref):
+                    return False
+        return True
+
     check("capacity", capacity)
+    check("batches", batches)
     return failed
 
 

@@ -322,6 +322,88 @@ def test_random_utf16_vs_cpython(orc):
             assert out[:len(ref)].tobytes() == ref
 
 
+def _units16_of_utf8(b: bytes) -> int:
+    """Reading 4 for UTF-8 input: one word per byte that is not a
+    continuation byte (10xxxxxx), one more per byte >= F0."""
+    a = np.frombuffer(b, dtype=np.uint8)
+    return int(np.count_nonzero((a & 0xC0) != 0x80) + np.count_nonzero(a >= 0xF0))
+
+
+def _units8_of_utf16(w: np.ndarray) -> int:
+    """Reading 4 for UTF-16LE input: 1, 2 or 3 bytes per word by value
+    (Section 3 ranges), 2 per surrogate word."""
+    w = w.astype(np.int64)
+    sur = (w >= 0xD800) & (w <= 0xDFFF)
+    return int(np.sum(np.where(w < 0x80, 1, np.where(w < 0x800, 2, np.where(sur, 2, 3)))))
+
+
+def _edit16(rng, w):
+    """Overwrite, delete or cut one word, biased toward surrogates."""
+    w = list(w)
+    if not w:
+        return w
+    p, op = int(rng.integers(0, len(w))), int(rng.integers(0, 3))
+    if op == 0:
+        w[p] = int(rng.choice([0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0x0041, 0x20AC]))
+    elif op == 1:
+        del w[p]
+    else:
+        w = w[:p]
+    return w
+
+
+def test_batch_conversions_vs_cpython_per_string(orc):
+    """Reading 9: in one batched call each string is converted as if alone
+    (status and position as CPython's strict codec finds them for that
+    string alone, exact output for a valid string) and its output starts at
+    the sum of the reading-4 lengths of the strings before it."""
+    rng = np.random.default_rng(15)
+    mixes = ("mix1m",) + SCRIPT_MIXES
+    for rep in range(40):
+        k = int(rng.integers(1, 60))
+        s8, s16 = [], []
+        for i in range(k):
+            t = random_text(rng, mixes[(rep + i) % len(mixes)], int(rng.integers(0, 30)))
+            b = bytearray(t.tobytes())
+            if b and rng.random() < 0.3:   # an invalid string: one byte edited, deleted or cut
+                p, op = int(rng.integers(0, len(b))), int(rng.integers(0, 3))
+                if op == 0:
+                    b[p] = int(EDGE8[rng.integers(0, EDGE8.size)])
+                elif op == 1:
+                    del b[p]
+                else:
+                    b = b[:p]
+            s8.append(bytes(b))
+            w = np.frombuffer(t.tobytes().decode("utf-8").encode("utf-16-le"), dtype="<u2")
+            if w.size and rng.random() < 0.3:
+                w = np.array(_edit16(rng, w), dtype=np.uint16)
+            s16.append(np.asarray(w, dtype=np.uint16))
+        # UTF-8 -> UTF-16LE
+        data = np.frombuffer(b"".join(s8) or b"\0", dtype=np.uint8)[:sum(map(len, s8))]
+        off = np.concatenate([[0], np.cumsum([len(x) for x in s8])]).astype(np.int64)
+        st, cnt, out, oo = orc.convert_utf8_to_utf16le_batch(data, off)
+        assert np.array_equal(oo, np.concatenate([[0], np.cumsum([_units16_of_utf8(x) for x in s8])]))
+        for i, x in enumerate(s8):
+            kind, pos, txt = cpy_utf8(x)
+            assert (st[i] == 0) == (kind == 0), (rep, i, x.hex())
+            if kind == 0:
+                ref = np.frombuffer(txt.encode("utf-16-le"), dtype="<u2")
+                assert cnt[i] == ref.size and np.array_equal(out[oo[i]:oo[i] + ref.size], ref), (rep, i)
+            else:
+                assert cnt[i] == pos, (rep, i, x.hex())
+        # UTF-16LE -> UTF-8
+        d16 = np.concatenate(s16).astype(np.uint16) if k else np.zeros(0, np.uint16)
+        off16 = np.concatenate([[0], np.cumsum([x.size for x in s16])]).astype(np.int64)
+        st, cnt, out, oo = orc.convert_utf16le_to_utf8_batch(d16, off16)
+        assert np.array_equal(oo, np.concatenate([[0], np.cumsum([_units8_of_utf16(x) for x in s16])]))
+        for i, x in enumerate(s16):
+            kind, pos, txt = cpy_utf16(x.astype("<u2").tobytes())
+            assert (st[i], cnt[i]) == ((0, len(txt.encode("utf-8"))) if kind == 0 else (kind, pos)), (rep, i, x)
+            if kind == 0:
+                ref = np.frombuffer(txt.encode("utf-8"), dtype=np.uint8)
+                assert np.array_equal(out[oo[i]:oo[i] + ref.size], ref), (rep, i)
+
+
 # --------------------------------------------------------------------------
 # invariants on generated text
 # --------------------------------------------------------------------------
