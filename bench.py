@@ -264,7 +264,8 @@ def serve_leg(reqs, small, aux):
         aux[f"serve_{tag}_launches"] = res.launches
     aux["serve_workload"] = (f"{reqs.arrival.size} requests, {int(reqs.size.sum())} bytes, Poisson 50k/s "
                              "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
-                             "directions, 0.5% invalid; each direction batched per pass, 4 streams")
+                             "directions, 0.5% invalid; each direction batched per pass, 4 streams, every stream's "
+                             "workspace pre-sized before timing")
     # the same, with the batched calls' geometry tuned on mixed-script text
     from paper_2111_08692_amd import tune
     try:
