@@ -96,10 +96,11 @@ int geometry_index(const char *name) {
 // 32 KiB tiles leave most CUs idle there.  Batched UTF-8 calls keep 8 KiB
 // tiles up to 16 MiB.  Larger batched UTF-16 calls use the 4 x 4 build:
 // serving runs them on several streams beside other look-back kernels, and
-// (the likely reading of the measurements) an 8-wave workgroup with 48 KiB
-// of LDS often finds no room on its XCD while later tiles of its own or
-// another kernel wait for it, so the wait lasts until the helping path
-// steps in; 4-wave workgroups fit beside the others (measured: twice the throughput
+// (the likely reading of the measurements) an 8-wave workgroup, which needs
+// registers for two 80-VGPR waves on every SIMD of one CU, often finds no
+// room on its XCD while later tiles of its own or another kernel wait for
+// it, so the wait lasts until the helping path steps in; a 4-wave
+// workgroup needs one wave per SIMD and fits beside the others (measured: twice the throughput
 // of 8 x 4 for a burst of requests on four streams, against up to 5 % less
 // for one call alone).  Everything else: the 8 x 4 build (16 KiB tiles win
 // on non-ASCII text and lose more on ASCII).
