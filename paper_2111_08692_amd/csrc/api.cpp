@@ -154,15 +154,21 @@ int utfgpu::lookback_spin_limit() {
     return limit;
 }
 
+u64 utfgpu::epoch_period() {
+    static const u64 period = [] {
+        constexpr u64 kMax = kEpochMask + 1;
+        const char *e = std::getenv("UTFGPU_EPOCH_PERIOD");
+        if (!e || !*e) return kMax;
+        const long long v = std::atoll(e);
+        return v < 2 ? (u64)2 : ((u64)v > kMax ? kMax : (u64)v);
+    }();
+    return period;
+}
+
 static_assert(sizeof(utf_result) == sizeof(DevResult), "result layout");
 static_assert(offsetof(utf_result, count) == offsetof(DevResult, count), "result layout");
 
 namespace {
-
-// Epoch values are 22 bits wide; the status array is cleared whenever the
-// host has issued this many tile launches on a workspace, so no stale word
-// from an earlier call can carry the current epoch.
-constexpr u64 kClearEvery = 1ull << 21;
 
 struct Workspace {
     int device = 0;
@@ -175,7 +181,6 @@ struct Workspace {
     u64 *partials = nullptr;     // device partial sums of the length reductions
     u64 *status = nullptr;       // device tile status words
     u64 status_cap = 0;
-    u64 launches = 0;
     // batched calls
     uint32_t *bad = nullptr;        // offsets check flag
     uint32_t *starts = nullptr;     // string-start bitmap (all zero between calls)
@@ -221,12 +226,7 @@ hipError_t make_ws(int dev, hipStream_t s, Workspace **out) {
     if ((e = hipMalloc(&w->partials, kMaxPartials * sizeof(u64))) != hipSuccess) goto fail;
     if ((e = hipHostMalloc(&w->hres, sizeof(DevResult), hipHostMallocDefault)) != hipSuccess) goto fail;
     if ((e = hipHostMalloc(&w->hlen, sizeof(u64), hipHostMallocDefault)) != hipSuccess) goto fail;
-    {
-        Ctrl init = {};
-        init.err = ~0ull;
-        init.epoch = 1;
-        if ((e = hipMemcpy(w->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice)) != hipSuccess) goto fail;
-    }
+    if ((e = base::launch_ctrl_init(w->ctrl, nullptr, 0, epoch_period(), s)) != hipSuccess) goto fail;
     *out = w;
     return hipSuccess;
 fail:
@@ -257,14 +257,9 @@ hipError_t get_ws(hipStream_t s, u64 ntiles, Workspace **out) {
         w->status_cap = 0;
         u64 cap = ntiles < 4096 ? 4096 : ntiles + ntiles / 4;
         if ((e = hipMalloc(&w->status, cap * kStatusStride * sizeof(u64))) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(w->status, 0, cap * kStatusStride * sizeof(u64), s)) != hipSuccess) return e;
+        // clears the new words and points the control block at them
+        if ((e = base::launch_ctrl_init(w->ctrl, w->status, cap, epoch_period(), s)) != hipSuccess) return e;
         w->status_cap = cap;
-    }
-    if (ntiles > 0) {
-        if (w->launches > 0 && w->launches % kClearEvery == 0) {
-            if ((e = hipMemsetAsync(w->status, 0, w->status_cap * kStatusStride * sizeof(u64), s)) != hipSuccess) return e;
-        }
-        w->launches++;
     }
     *out = w;
     return hipSuccess;

@@ -89,16 +89,23 @@ struct DevResult {
     u64 count;
 };
 
-// Per-workspace control block, each field on its own 64-byte line.  The
-// finalize kernel of every call resets `err` and `total` and advances
-// `epoch`, so each call finds it in the same state.
+// Per-workspace control block, the fields the tiles write each on its own
+// 64-byte line.  The finalize kernel of every call resets `err` and
+// `total` and advances `epoch`, so each call finds it in the same state.
+// Epochs run 1 .. period-1; the call whose finalize would reach `period`
+// clears every status word of the workspace and starts again at 1, so a
+// status word left by an earlier call never carries the current epoch,
+// however many calls (eager or replayed from a captured graph) ran.
 struct Ctrl {
     u64 err;        // min over (position << 4 | kind); ~0 when no error
     u64 pad0[7];
     u64 total;      // output units of the whole call (written by the last tile)
     u64 pad1[7];
     u64 epoch;      // tag of the status words of the current call
-    u64 pad2[7];
+    u64 period;     // at most 2^22 (the epoch field of a status word)
+    u64 *status;    // the workspace's status words, kStatusStride words apart
+    u64 status_cap; // number of status words
+    u64 pad2[4];
 };
 
 // ------------------------------------------------------------------------
@@ -511,7 +518,16 @@ enum : int { kFinValidate = 0, kFinConvert = 1, kFinLength = 2 };
 namespace UTF_GEOM {
 hipError_t launch_finalize(Ctrl *ctrl, DevResult *result, u64 *len_result, int mode, u64 n, u64 out_cap,
                            const u64 *partials, int npartials, hipStream_t stream);
+// Set a control block up for a status array of `status_cap` words (all of
+// which are cleared): no error, total 0, epoch 1, epochs wrapping at
+// `period`.  Used when a workspace is made and when its status array is
+// replaced by a larger one.
+hipError_t launch_ctrl_init(Ctrl *ctrl, u64 *status, u64 status_cap, u64 period, hipStream_t stream);
 }  // namespace UTF_GEOM
+
+// Epoch period of new control blocks: UTFGPU_EPOCH_PERIOD when set (2 ..
+// 2^22; small values exercise the wrap), else 2^22.
+u64 epoch_period();
 
 // Look-back probes before a wave computes a silent predecessor's aggregate
 // itself: UTFGPU_LOOKBACK_SPINS when set (0 exercises the helping path on

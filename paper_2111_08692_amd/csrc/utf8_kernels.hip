@@ -1238,6 +1238,15 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(Ctrl *ctrl, DevResult 
         }
         return;
     }
+    // the call that would reach the period clears the status words
+    const u64 next = ld_agent(&ctrl->epoch) + 1;
+    const bool wrap = next >= ctrl->period;
+    __syncthreads();   // every thread has read the epoch before thread 0 advances it
+    if (wrap) {
+        u64 *st = ctrl->status;
+        const u64 cap = ctrl->status_cap;
+        for (u64 t = tid; t < cap; t += kBlock) st_agent(st + t * kStatusStride, 0);
+    }
     if (tid != 0) return;
     const u64 e = ld_agent(&ctrl->err);
     if (e != ~0ull) {
@@ -1254,7 +1263,21 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(Ctrl *ctrl, DevResult 
     result->pad = 0;
     st_agent(&ctrl->err, ~0ull);
     st_agent(&ctrl->total, 0);
-    st_agent(&ctrl->epoch, ld_agent(&ctrl->epoch) + 1);
+    st_agent(&ctrl->epoch, wrap ? 1 : next);
+}
+
+__global__ __launch_bounds__(kBlock) void ctrl_init_kernel(Ctrl *ctrl, u64 *status, u64 status_cap, u64 period) {
+    const uint32_t tid = threadIdx.x;
+    for (u64 t = (u64)blockIdx.x * kBlock + tid; t < status_cap; t += (u64)gridDim.x * kBlock)
+        status[t * kStatusStride] = 0;
+    if (blockIdx.x == 0 && tid == 0) {
+        ctrl->err = ~0ull;
+        ctrl->total = 0;
+        ctrl->epoch = 1;
+        ctrl->period = period;
+        ctrl->status = status;
+        ctrl->status_cap = status_cap;
+    }
 }
 
 // Results of empty inputs for the asynchronous calls (a kernel rather than
@@ -1445,6 +1468,13 @@ hipError_t launch_finalize(Ctrl *ctrl, DevResult *result, u64 *len_result, int m
                            const u64 *partials, int npartials, hipStream_t stream) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, stream, ctrl, result, len_result, mode, n,
                        out_cap, partials, npartials);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl *ctrl, u64 *status, u64 status_cap, u64 period, hipStream_t stream) {
+    const u64 blocks = (status_cap + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(ctrl_init_kernel, dim3((unsigned)(blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks))),
+                       dim3(kBlock), 0, stream, ctrl, status, status_cap, period);
     return hipGetLastError();
 }
 

@@ -1,21 +1,25 @@
 """Continuous-batching transcoding server over the C ABI (one GPU).
 
-Requests arrive open-loop (each has an arrival time); the scheduler loop, on
-every pass:
+Requests arrive open-loop (each has an arrival time).  Output space comes
+from one device-resident arena whose size is set from the device's free HBM
+when the server starts: the free memory reported by the runtime, less a
+reserve left for the library's workspaces and other users, capped by a
+configurable budget.  The scheduler loop, on every pass:
 
 * takes the requests that have arrived and admits them while their output
-  fits in the output pool of their direction (HBM is reserved per request
-  for the worst case of any input: 4 bytes per input byte for UTF-8 ->
-  UTF-16LE, since a byte >= F0 counts two words even in an invalid request
-  and the offsets of the requests after it include them; 3 bytes per input
-  unit for UTF-16LE -> UTF-8);
+  fits in the arena (space is reserved per request for the worst case of
+  any input: 4 bytes per input byte for UTF-8 -> UTF-16LE, since a byte
+  >= F0 counts two words even in an invalid request and the offsets of the
+  requests after it include them; 3 bytes per input unit for UTF-16LE ->
+  UTF-8); requests that do not fit are held back until completions free
+  space;
 * launches the admitted requests of each direction as ONE batched call
   (their payloads lie back to back in device memory) on the next of
   ``nstreams`` streams, and queues a device-to-host copy of their results
   behind it;
 * polls the events of the launches in flight, stamps the completion time of
-  every finished one, and frees output space in launch order (the pools
-  are rings).
+  every finished one, and frees arena space in launch order (the arena is
+  a ring).
 
 Latency is completion time minus arrival time; throughput is input bytes
 over the span from the first arrival to the last completion.  Every
@@ -45,8 +49,10 @@ class _Flight:
 
 @dataclass
 class ServeResult:
-    """Per request: status, count, output offset (units, in the output pool
-    of its direction) and latency (s); plus the run's totals."""
+    """Per request: status, count, output offset (bytes into the output
+    arena) and latency (s); plus the run's totals: ``held_back`` requests
+    arrived while the arena had no room for them and waited for
+    completions (``held_passes`` scheduler passes refused a batch)."""
     status: np.ndarray
     count: np.ndarray
     out_off: np.ndarray
@@ -55,6 +61,8 @@ class ServeResult:
     input_bytes: int
     launches: int
     max_inflight: int
+    held_back: int = 0
+    held_passes: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -66,7 +74,7 @@ class ServeResult:
 
 
 class _Ring:
-    """Byte ring over an output pool; frees in allocation order."""
+    """Byte ring over an output arena; frees in allocation order."""
 
     def __init__(self, size: int):
         self.size = size
@@ -76,7 +84,7 @@ class _Ring:
     def alloc(self, nbytes: int) -> Optional[Tuple[int, int]]:
         """(start, bytes charged) or None when it does not fit now."""
         if nbytes > self.size:
-            raise ValueError("request larger than the output pool")
+            raise ValueError("request larger than the output arena")
         start, waste = self.head, 0
         if start + nbytes > self.size:   # does not fit before the end: start over at 0
             waste, start = self.size - start, 0
@@ -88,6 +96,18 @@ class _Ring:
 
     def free(self, nbytes: int) -> None:
         self.used -= nbytes
+        if self.used == 0:   # empty: the next allocation may use the whole ring
+            self.head = 0
+
+
+ALIGN = 256   # arena reservations start on 256-byte boundaries
+
+
+def reservation(kind: int, units: int) -> int:
+    """Arena bytes reserved for ``units`` input units of direction ``kind``
+    (the worst-case output of any input, rounded up to ``ALIGN``)."""
+    per_unit = 4 if kind == 0 else 3
+    return -(-per_unit * int(units) // ALIGN) * ALIGN
 
 
 def prewarm_windows(off: np.ndarray, kind: int, max_batch_bytes: int, pool_bytes: int) -> List[Tuple[int, int]]:
@@ -115,11 +135,16 @@ def prewarm_windows(off: np.ndarray, kind: int, max_batch_bytes: int, pool_bytes
 
 
 class Server:
-    """Device-resident payload arenas, per-direction output pools and a
-    stream pool.  ``reqs`` is a ``workloads.RequestSet``."""
+    """Device-resident payload arenas, one output arena sized from free HBM
+    and a stream pool.  ``reqs`` is a ``workloads.RequestSet``.
 
-    def __init__(self, reqs, nstreams: int = 4, pool_bytes: int = 4 << 30, max_inflight: int = 16,
-                 max_batch_bytes: int = 256 << 20, device: str = "cuda"):
+    The output arena takes ``min(hbm_budget, free HBM - hbm_reserve)`` bytes,
+    the free HBM being read from the runtime after the payloads are on the
+    device.  Its size is ``arena_bytes``; a request whose reservation alone
+    exceeds it is refused at construction."""
+
+    def __init__(self, reqs, nstreams: int = 4, hbm_budget: int = 8 << 30, hbm_reserve: int = 2 << 30,
+                 max_inflight: int = 16, max_batch_bytes: int = 256 << 20, device: str = "cuda"):
         load()
         self.r = reqs
         self.dev = torch.device(device)
@@ -128,9 +153,19 @@ class Server:
         self.d16 = torch.from_numpy(reqs.data16.view(np.int16)).to(self.dev)
         self.off8_dev = torch.from_numpy(reqs.off8).to(self.dev)
         self.off16_dev = torch.from_numpy(reqs.off16).to(self.dev)
-        self.pool_bytes = int(pool_bytes)
-        self.out16 = torch.empty(self.pool_bytes // 2, dtype=torch.int16, device=self.dev)   # UTF-16 words
-        self.out8 = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.dev)         # UTF-8 bytes
+        torch.cuda.synchronize(self.dev)
+        free, _ = torch.cuda.mem_get_info(self.dev)
+        self.free_hbm_at_start = int(free)
+        arena = min(int(hbm_budget), int(free) - int(hbm_reserve))
+        self.arena_bytes = max(arena, 0) // ALIGN * ALIGN
+        largest = max([reservation(0, int(d)) for d in np.diff(reqs.off8)] +
+                      [reservation(1, int(d)) for d in np.diff(reqs.off16)] + [0])
+        if largest > self.arena_bytes:
+            raise ValueError(f"the output arena ({self.arena_bytes} bytes: budget {hbm_budget}, free HBM {free}, "
+                             f"reserve {hbm_reserve}) cannot hold the largest request ({largest} bytes)")
+        self.arena = torch.empty(max(self.arena_bytes, ALIGN), dtype=torch.uint8, device=self.dev)
+        self.out16 = self.arena.view(torch.int16)   # UTF-16 words (reservations start on even bytes)
+        self.out8 = self.arena
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(nstreams)]          # default priority
         self.max_inflight = max_inflight
         self.max_batch_bytes = max_batch_bytes
@@ -143,8 +178,8 @@ class Server:
     def _launch(self, kind: int, i: int, j: int, start: int, s: torch.cuda.Stream):
         """One batched call on stream ``s`` over positions i..j-1 of the
         queue of direction ``kind`` (0: UTF-8 -> UTF-16LE), output from byte
-        ``start`` of that direction's pool; returns the device output
-        offsets and results."""
+        ``start`` of the arena (a multiple of ``ALIGN``); returns the device
+        output offsets and results."""
         off_k, off_dev = (self.r.off8, self.off8_dev) if kind == 0 else (self.r.off16, self.off16_dev)
         k, nu = j - i, int(off_k[j] - off_k[i])
         with torch.cuda.stream(s):
@@ -171,10 +206,10 @@ class Server:
         and stream, one batched call over the window of queued requests
         with the most input and one over the window with the most requests,
         each as long as ``run`` may form a batch (the batch limit and the
-        output pool).  Run it again after changing the geometry table."""
+        output arena).  Run it again after changing the geometry table."""
         r = self.r
         for kind, off in ((0, r.off8), (1, r.off16)):
-            wins = prewarm_windows(off, kind, self.max_batch_bytes, self.pool_bytes)
+            wins = prewarm_windows(off, kind, self.max_batch_bytes, self.arena_bytes)
             for s in self.streams:
                 for i, j in wins:
                     self._launch(kind, i, j, 0, s)
@@ -190,14 +225,15 @@ class Server:
         arr16 = arr[r.ids16] if r.ids16.size else np.zeros(0)
         out_off = np.full(n, -1, dtype=np.int64)
         done_t = np.zeros(n)
-        rings = (_Ring(self.pool_bytes), _Ring(self.pool_bytes))
+        ring = _Ring(self.arena_bytes)
         inflight: Deque[_Flight] = collections.deque()
-        batch_offsets = []   # (ids, device out_offsets, pool word base) of the batched launches
+        batch_offsets = []   # (ids, device out_offsets, arena byte base, kind) of the batched launches
         queue = [{"arr": arr8, "off": r.off8, "off_dev": self.off8_dev, "ids": r.ids8, "host": self.res8_host,
                   "next": 0},
                  {"arr": arr16, "off": r.off16, "off_dev": self.off16_dev, "ids": r.ids16, "host": self.res16_host,
                   "next": 0}]
-        finished = launches = max_inflight = si = 0
+        finished = launches = max_inflight = si = held_passes = 0
+        held = np.zeros(n, dtype=bool)   # requests that arrived and had to wait for arena space
         t0 = time.perf_counter()
         while finished < n:
             now = time.perf_counter() - t0
@@ -209,20 +245,20 @@ class Server:
                 i = q["next"]
                 if i >= arr_k.size or arr_k[i] > now or len(inflight) >= self.max_inflight:
                     continue
-                # worst-case output bytes per input unit, for any input: a UTF-8
-                # byte >= F0 counts two words even in an invalid string, and the
-                # offsets of the strings after it include them
-                per_unit = 4 if kind == 0 else 3
                 j = max(int(np.searchsorted(arr_k, now, side="right")), i + 1)
                 lim = int(np.searchsorted(off_k, off_k[i] + self.max_batch_bytes // (1 + kind), side="right")) - 1
                 j = min(j, max(lim, i + 1))
-                got = rings[kind].alloc(per_unit * int(off_k[j] - off_k[i]))
+                got = ring.alloc(reservation(kind, int(off_k[j] - off_k[i])))
                 while got is None and j > i + 1:   # admit a shorter prefix of the queue
                     j = i + (j - i) // 2
-                    got = rings[kind].alloc(per_unit * int(off_k[j] - off_k[i]))
-                if got is None:
+                    got = ring.alloc(reservation(kind, int(off_k[j] - off_k[i])))
+                if got is None:   # held back until completions free arena space
+                    if not inflight and ring.used == 0:
+                        raise RuntimeError(f"request {int(q['ids'][i])} cannot be admitted into an empty arena")
+                    held[q["ids"][i:max(int(np.searchsorted(arr_k, now, side="right")), i + 1)]] = True
+                    held_passes += 1
                     continue
-                start, held = got
+                start, charged = got
                 k = j - i
                 s = self.streams[si % len(self.streams)]
                 si += 1
@@ -232,8 +268,8 @@ class Server:
                     ev = torch.cuda.Event()
                     ev.record(s)
                 ids = q["ids"][i:j]
-                batch_offsets.append((ids, oo, start // 2 if kind == 0 else start))
-                inflight.append(_Flight(ev, ids, kind, held))
+                batch_offsets.append((ids, oo, start, kind))
+                inflight.append(_Flight(ev, ids, kind, charged))
                 q["next"] = j
                 launches += 1
                 launched = True
@@ -248,7 +284,7 @@ class Server:
             freed = False
             while inflight and inflight[0].done:
                 f = inflight.popleft()
-                rings[f.kind].free(f.held)
+                ring.free(f.held)
                 freed = True
             if not launched and not freed:
                 if inflight:
@@ -259,8 +295,8 @@ class Server:
                     if wait > 0.0005:
                         time.sleep(wait - 0.0003)
         torch.cuda.synchronize()
-        for ids, oo, base in batch_offsets:
-            out_off[ids] = base + oo[:-1].cpu().numpy()
+        for ids, oo, base, kind in batch_offsets:   # arena byte offsets
+            out_off[ids] = base + (2 if kind == 0 else 1) * oo[:-1].cpu().numpy()
         status = np.zeros(n, dtype=np.int32)
         count = np.zeros(n, dtype=np.int64)
         for ids, host, m in ((r.ids8, self.res8_host, r.ids8.size), (r.ids16, self.res16_host, r.ids16.size)):
@@ -271,13 +307,14 @@ class Server:
         latency = done_t - arr
         span = float(done_t.max() - arr.min()) if n else 0.0
         return ServeResult(status=status, count=count, out_off=out_off, latency=latency, span_s=span,
-                           input_bytes=int(r.size.sum()), launches=launches, max_inflight=max_inflight)
+                           input_bytes=int(r.size.sum()), launches=launches, max_inflight=max_inflight,
+                           held_back=int(held.sum()), held_passes=held_passes)
 
     def output_of(self, res: ServeResult, rid: int) -> np.ndarray:
         """The output units of request ``rid`` after ``run`` (a valid request;
-        only while later requests have not reused its space: the pools are
-        rings, so this holds when a run's outputs fit the pool)."""
+        only while later requests have not reused its space: the arena is a
+        ring, so this holds when a run's outputs fit the arena)."""
         cnt, o = int(res.count[rid]), int(res.out_off[rid])
         if self.r.kind[rid] == 0:
-            return self.out16[o:o + cnt].cpu().numpy().view(np.uint16)
-        return self.out8[o:o + cnt].cpu().numpy()
+            return self.arena[o:o + 2 * cnt].cpu().numpy().view(np.uint16)
+        return self.arena[o:o + cnt].cpu().numpy()

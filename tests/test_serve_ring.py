@@ -3,7 +3,7 @@ that pre-size the library's workspaces (no GPU)."""
 import numpy as np
 import pytest
 
-from paper_2111_08692_amd.serve import _Ring, prewarm_windows
+from paper_2111_08692_amd.serve import ALIGN, _Ring, prewarm_windows, reservation
 
 
 def test_ring_alloc_free_wrap():
@@ -18,6 +18,23 @@ def test_ring_alloc_free_wrap():
     r.free(40)
     r.free(50)
     assert r.used == 0
+
+
+def test_ring_empty_starts_over():
+    """Once everything is freed the next reservation may take the whole
+    ring, wherever the last one ended."""
+    r = _Ring(100)
+    assert r.alloc(50) == (0, 50)
+    r.free(50)
+    assert r.head == 0 and r.used == 0
+    assert r.alloc(60) == (0, 60)
+    r.free(60)
+    assert r.alloc(100) == (0, 100)
+
+
+def test_reservation_is_aligned_worst_case():
+    assert reservation(0, 1) == ALIGN and reservation(0, 64) == 256 and reservation(0, 65) == 512
+    assert reservation(1, 100) == 512 and reservation(1, 85) == 256 and reservation(1, 0) == 0
 
 
 def test_ring_rejects_oversize():
