@@ -16,8 +16,10 @@ results back to the host.  ``value`` is input bytes per second over the
 timed steps.  Per-launch HIP events give every kernel's duration; the
 roofline entry is the dominant kernel's algorithmic bytes (input read +
 output written) per second against the 8 TB/s HBM peak.  The length and
-validate-only kernels, the 1 MiB single-buffer latency and the CPU oracle
-(on a bounded sample of the same buffers, one core) are reported beside it.
+validate-only kernels, the 1 MiB single-buffer latency, the batched and
+served workloads (each beside plain single-buffer calls on the same bytes)
+and the CPU oracle (on the host's cores, and on one core over a bounded
+sample, with the CPU model) are reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib S]
 """
@@ -112,10 +114,41 @@ def cut_utf16(a: np.ndarray, m: int) -> np.ndarray:
     return a[:m]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _slices(a: np.ndarray, enc: str, parts: int):
+    """``parts`` consecutive slices of ``a`` cut at character starts (a cut is
+    moved forward past continuation bytes / low surrogates)."""
+    cuts = [0]
+    for k in range(1, parts):
+        c = max(cuts[-1], a.size * k // parts)
+        if enc == "utf-8":
+            while c < a.size and (a[c] & 0xC0) == 0x80:
+                c += 1
+        elif c < a.size and 0xDC00 <= a[c] <= 0xDFFF:
+            c += 1
+        cuts.append(c)
+    cuts.append(a.size)
+    return [a[cuts[i]:cuts[i + 1]] for i in range(parts)]
+
+
 def cpu_baseline(bufs, sample_bytes: int):
-    """The oracle, single-threaded, on the first ``sample_bytes`` of every
-    valid buffer, both directions."""
+    """The oracle on the host: one thread on the first ``sample_bytes`` of
+    every valid buffer, and all the host's cores on the whole valid buffers
+    (each buffer cut at character starts into one slice per thread, every
+    slice converted on its own; the oracle's C calls release the GIL, so
+    the threads run in parallel)."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     oracle.build(force=False)
     total_in = 0
     total_t = 0.0
@@ -135,9 +168,26 @@ def cpu_baseline(bufs, sample_bytes: int):
             total_t += time.perf_counter() - t
             total_in += 2 * s.size
         assert st == 0, (mix, enc, st)
-    return {"value": round(total_in / total_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_bytes >> 20} MiB of each of the 10 valid buffers (5 mixes x 2 directions), "
-                      f"{total_in / 2**30:.2f} GiB input, {total_t:.1f} s"}
+    one_core = total_in / total_t / 1e9
+    threads = len(os.sched_getaffinity(0))
+    all_in, all_t = 0, 0.0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for mix, enc, kind, b in bufs:
+            if kind != "valid":
+                continue
+            conv = oracle.convert_utf8_to_utf16le if enc == "utf-8" else oracle.convert_utf16le_to_utf8
+            parts = _slices(b.data, enc, threads)
+            t = time.perf_counter()
+            res = list(ex.map(conv, parts))
+            all_t += time.perf_counter() - t
+            all_in += b.data.nbytes
+            assert all(r[0] == 0 for r in res), (mix, enc)
+            del res
+    return {"value": round(all_in / all_t / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"all-core: the 10 valid buffers whole ({all_in / 2**30:.1f} GiB, {threads} threads, each "
+                      f"buffer cut at character starts into one slice per thread), {all_t:.1f} s; one core: first "
+                      f"{sample_bytes >> 20} MiB of each, {total_in / 2**30:.2f} GiB, {total_t:.1f} s",
+            "single_core_GBps": round(one_core, 4), "cpu_model": cpu_model(), "host_threads": threads}
 
 
 # ---------------------------------------------------------------------------
@@ -234,7 +284,23 @@ def batch_leg(G, dev, stream, aux):
         G.convert_utf8_to_utf16le_async(d[a:e], out[int(ooff[i]):], res1[i], out_cap=int(ooff[i + 1] - ooff[i]))
     torch.cuda.synchronize()
     tloop = time.perf_counter() - t0
+    # one plain single-buffer call over the same concatenated bytes (the
+    # strings' boundaries ignored): the rate the batched call is compared with
+    o1 = torch.empty(b.data.size, dtype=torch.int16, device=dev)
+    r1 = G.result_tensor(device=dev)
+    for _ in range(3):
+        G.convert_utf8_to_utf16le_async(d, o1, r1)
+    ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for s_, e_ in ev1:
+        s_.record(stream)
+        G.convert_utf8_to_utf16le_async(d, o1, r1)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    t1 = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev1) / 1e3
+    del o1
     alg = b.data.size + 2 * total
+    aux["batch100k_single_buffer_call_ms"] = round(t1 * 1e3, 3)
+    aux["batch100k_time_vs_single_buffer"] = round(t / t1, 3)
     aux["batch100k_workload"] = (f"{k} UTF-8 strings, {b.data.size} bytes, log-normal lengths (median 256 B, "
                                  "sigma 1.5, 16 B..1 MiB), one script mix each, 1% with one error")
     aux["batch100k_call_ms"] = round(t * 1e3, 3)
@@ -252,9 +318,28 @@ def serve_leg(reqs, small, aux):
     (saturation); then the open-loop replay again with the geometry tuner's
     table for the batched calls (tuned on the 1 MiB mixed-script text)."""
     from paper_2111_08692_amd.serve import Server
+    import torch
+    import paper_2111_08692_amd as G
     srv = Server(reqs, nstreams=4)
     srv.prewarm()             # every stream's workspace at its final size
     srv.run(time_scale=0.0)   # warm-up (allocator)
+    # the same bytes as two plain single-buffer calls (each direction's
+    # payloads back to back, request boundaries ignored): the rate the
+    # served throughput is compared with
+    o16 = torch.empty(srv.d8.numel(), dtype=torch.int16, device=srv.dev)
+    o8 = torch.empty(3 * srv.d16.numel(), dtype=torch.uint8, device=srv.dev)
+    rr = G.result_tensor(device=srv.dev)
+    times = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G.convert_utf8_to_utf16le_async(srv.d8, o16, rr)
+        G.convert_utf16le_to_utf8_async(srv.d16, o8, rr)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(time.perf_counter() - t)
+    aux["serve_single_buffer_GBps"] = round(int(reqs.size.sum()) / min(times) / 1e9, 1)
+    del o16, o8
     for tag, scale in (("50k_rps", 1.0), ("burst", 0.0)):
         res = srv.run(time_scale=scale)
         assert np.all(res.status[~reqs.invalid] == 0), "valid request failed"
@@ -262,10 +347,34 @@ def serve_leg(reqs, small, aux):
         aux[f"serve_{tag}_p99_us"] = round(res.percentile_us(99), 1)
         aux[f"serve_{tag}_GBps"] = round(res.gbps, 2)
         aux[f"serve_{tag}_launches"] = res.launches
+    aux["serve_burst_vs_single_buffer"] = round(aux["serve_burst_GBps"] / aux["serve_single_buffer_GBps"], 3)
+    # served outputs against single-buffer calls on the same payloads: a
+    # seeded sample and the largest requests, from an extra all-at-once run
+    # that copies each launch's output as it completes
+    res = srv.run(time_scale=0.0, collect=True)
+    rng = np.random.default_rng(604)
+    ids = set(rng.choice(reqs.arrival.size, size=300, replace=False).tolist())
+    ids |= set(np.argsort(reqs.size)[-20:].tolist())
+    for rid in sorted(ids):
+        kind = int(reqs.kind[rid])
+        if kind == 0:
+            j = int(np.searchsorted(reqs.ids8, rid))
+            p = srv.d8[int(reqs.off8[j]):int(reqs.off8[j + 1])]
+            st, cnt, out = G.convert_utf8_to_utf16le(p)
+        else:
+            j = int(np.searchsorted(reqs.ids16, rid))
+            p = srv.d16[int(reqs.off16[j]):int(reqs.off16[j + 1])]
+            st, cnt, out = G.convert_utf16le_to_utf8(p)
+        assert (int(res.status[rid]), int(res.count[rid])) == (st, cnt), ("served result", rid)
+        if st == 0:
+            alone = out[:cnt].cpu().numpy()
+            alone = alone.view(np.uint16) if kind == 0 else alone
+            assert np.array_equal(srv.output_of(res, rid), alone), ("served output", rid)
+    aux["serve_checked_requests"] = len(ids)
     aux["serve_workload"] = (f"{reqs.arrival.size} requests, {int(reqs.size.sum())} bytes, Poisson 50k/s "
                              "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
-                             "directions, 0.5% invalid; each direction batched per pass, 4 streams, every stream's "
-                             "workspace pre-sized before timing")
+                             "directions, 0.5% invalid; each direction batched per pass, 4 streams, one output arena "
+                             "sized from free HBM (8 GiB budget), every stream's workspace pre-sized before timing")
     # the same, with the batched calls' geometry tuned on mixed-script text
     from paper_2111_08692_amd import tune
     try:
@@ -523,9 +632,29 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"per_buffer": per, "aux": aux, "kernel_hash": kernel_hash(),
-                   "device": torch.cuda.get_device_name(0), "host_cores": os.cpu_count()},
+                   "device": torch.cuda.get_device_name(0), "host_cores": os.cpu_count(),
+                   "host_cores_usable": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()},
     }
     print(json.dumps(line), flush=True)
+    reap_children()
+
+
+def reap_children():
+    """Wait for (and report) any child process still alive at the end, so
+    that the benchmark leaves none behind."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    if kids:
+        log(f"{len(kids)} child process(es) left at the end: {[k.pid for k in kids]}; stopping them")
+        for k in kids:
+            try:
+                k.terminate()
+            except psutil.Error:
+                pass
+        psutil.wait_procs(kids, timeout=5)
 
 
 if __name__ == "__main__":

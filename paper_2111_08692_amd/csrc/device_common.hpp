@@ -136,13 +136,22 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// Inclusive prefix sum over the 64 lanes.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t t = __shfl_up(v, d);
-        if (lane >= (uint32_t)d) v += t;
-    }
+// Inclusive prefix sum over the 64 lanes with DPP: shifts by 1, 2, 4 and 8
+// lanes within each row of 16 (lanes shifted in from outside the row read
+// 0), then the last lane of row 0 / row 2 added to rows 1 / 3, then lane 31
+// added to rows 2 and 3.  Six adds, no LDS traffic.  (`lane` is unused: the
+// DPP row controls select the lanes.)
+constexpr int kDppRowShr = 0x110;     // row_shr:n is kDppRowShr + n
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t /*lane*/) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr + 1, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr + 2, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr + 4, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr + 8, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xC, 0xF, false);
     return v;
 }
 
@@ -166,6 +175,33 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// a + byte k of b (k = 0..3, a constant after unrolling) in one
+// instruction: v_add_u32 with an SDWA byte select on its second source.
+// Running slot offsets use it to advance by a per-byte step taken from a
+// register that holds the steps of four byte positions.
+__device__ __forceinline__ uint32_t add_byte(uint32_t a, uint32_t b, int k) {
+    uint32_t d;
+    switch (k) {
+        case 0:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+                : "=v"(d) : "v"(a), "v"(b));
+            break;
+        case 1:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+                : "=v"(d) : "v"(a), "v"(b));
+            break;
+        case 2:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+                : "=v"(d) : "v"(a), "v"(b));
+            break;
+        default:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+                : "=v"(d) : "v"(a), "v"(b));
+            break;
+    }
+    return d;
 }
 
 // bytes k..k+3 of the 8-byte little-endian pair (lo, hi)
@@ -333,6 +369,16 @@ __device__ __forceinline__ u64 owner_near(const BatchCtx &bc, long long w, long 
 // ------------------------------------------------------------------------
 // Write-out of staged output
 // ------------------------------------------------------------------------
+// Output addresses are computed as integers; gptr turns one back into a
+// pointer in the global address space, so the stores are global_store
+// instructions.  (A plain pointer made from an integer is a generic one:
+// flat stores, which also count against the LDS wait counter and so hold
+// back every later LDS wait of the wave.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(uintptr_t a) {
+    return (__attribute__((address_space(1))) T *)a;
+}
+
 // The output occupies bytes [g0, g0 + nbytes) of global memory.  `stage`
 // (LDS, dword aligned) holds those bytes starting at stage byte 0.  Whole
 // 16-byte aligned global blocks are written with one dwordx4 store each;
@@ -362,15 +408,15 @@ __device__ __forceinline__ void write_out(uint8_t *g0p, u64 nbytes, const uint32
                 v.z = __builtin_amdgcn_alignbyte(a3, a2, shift);
                 v.w = __builtin_amdgcn_alignbyte(a4, a3, shift);
             }
-            __builtin_nontemporal_store(v, (u32x4 *)c);
+            __builtin_nontemporal_store(v, gptr<u32x4>(c));
         } else {
             for (uintptr_t a = c; a < c + 16; a += kUnit) {
                 if (a >= g0 && a < g1) {
                     const uintptr_t so = a - g0;
                     if (kUnit == 2)
-                        *(uint16_t *)a = *(const uint16_t *)(sb + so);
+                        *gptr<uint16_t>(a) = *(const uint16_t *)(sb + so);
                     else
-                        *(uint8_t *)a = sb[so];
+                        *gptr<uint8_t>(a) = sb[so];
                 }
             }
         }
@@ -392,15 +438,15 @@ __device__ __forceinline__ void write_out_aligned(uint8_t *g0p, u64 nbytes, cons
         const uint32_t so = (uint32_t)(c - c0);
         if (c >= g0 && c + 16 <= g1) {
             const u32x4 v = *(const u32x4 *)(sb + so);
-            __builtin_nontemporal_store(v, (u32x4 *)c);
+            __builtin_nontemporal_store(v, gptr<u32x4>(c));
         } else {
             for (uint32_t k = 0; k < 16; k += kUnit) {
                 const uintptr_t a = c + k;
                 if (a >= g0 && a < g1) {
                     if (kUnit == 2)
-                        *(uint16_t *)a = *(const uint16_t *)(sb + so + k);
+                        *gptr<uint16_t>(a) = *(const uint16_t *)(sb + so + k);
                     else
-                        *(uint8_t *)a = sb[so + k];
+                        *gptr<uint8_t>(a) = sb[so + k];
                 }
             }
         }
@@ -429,10 +475,10 @@ __device__ __forceinline__ void store_part(uintptr_t c, uintptr_t a, uintptr_t b
     for (int sz = kUnit; sz <= 8; sz <<= 1) {   // up to the first 16-byte aligned chunk
         if ((a & (uintptr_t)sz) && a + sz <= b) {
             const uint32_t o = so + (uint32_t)(a - c);
-            if (sz == 1) *(uint8_t *)a = sb[o];
-            if (sz == 2) *(uint16_t *)a = *(const uint16_t *)(sb + o);
-            if (sz == 4) *(uint32_t *)a = *(const uint32_t *)(sb + o);
-            if (sz == 8) *(uint64_t *)a = *(const uint64_t *)(sb + o);
+            if (sz == 1) *gptr<uint8_t>(a) = sb[o];
+            if (sz == 2) *gptr<uint16_t>(a) = *(const uint16_t *)(sb + o);
+            if (sz == 4) *gptr<uint32_t>(a) = *(const uint32_t *)(sb + o);
+            if (sz == 8) *gptr<uint64_t>(a) = *(const uint64_t *)(sb + o);
             a += sz;
         }
     }
@@ -440,10 +486,10 @@ __device__ __forceinline__ void store_part(uintptr_t c, uintptr_t a, uintptr_t b
     for (int sz = 8; sz >= kUnit; sz >>= 1) {   // the rest, largest first
         if (a + sz <= b) {
             const uint32_t o = so + (uint32_t)(a - c);
-            if (sz == 1) *(uint8_t *)a = sb[o];
-            if (sz == 2) *(uint16_t *)a = *(const uint16_t *)(sb + o);
-            if (sz == 4) *(uint32_t *)a = *(const uint32_t *)(sb + o);
-            if (sz == 8) *(uint64_t *)a = *(const uint64_t *)(sb + o);
+            if (sz == 1) *gptr<uint8_t>(a) = sb[o];
+            if (sz == 2) *gptr<uint16_t>(a) = *(const uint16_t *)(sb + o);
+            if (sz == 4) *gptr<uint32_t>(a) = *(const uint32_t *)(sb + o);
+            if (sz == 8) *gptr<uint64_t>(a) = *(const uint64_t *)(sb + o);
             a += sz;
         }
     }
@@ -484,7 +530,7 @@ __device__ __forceinline__ void write_row(uintptr_t g0, uintptr_t g1, uintptr_t 
         for (uintptr_t c = c0 + 16 * (uintptr_t)lane; c < hi; c += 16 * kWave) {
             const uint32_t so = (uint32_t)(c - c0);
             if (c >= lo)
-                __builtin_nontemporal_store(*(const u32x4 *)(sb + so), (u32x4 *)c);
+                __builtin_nontemporal_store(*(const u32x4 *)(sb + so), gptr<u32x4>(c));
             else
                 store_part<kUnit>(c, lo, c + 16, sb, so);
         }

@@ -443,7 +443,7 @@ __device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g
         const uint32_t hi = __builtin_amdgcn_perm(t.d[r][3], t.d[r][2], 0x06040200u);
         const uint32_t q = 64u * (uint32_t)r + lane;
         if (s8 == 0) {
-            *(uint2 *)(g0 + 8u * q) = make_uint2(lo, hi);
+            *gptr<uint64_t>(g0 + 8u * q) = (uint64_t)hi << 32 | lo;
             continue;
         }
         uint32_t plo = __shfl_up(lo, 1), phi = __shfl_up(hi, 1);
@@ -462,17 +462,17 @@ __device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g
             b = __builtin_amdgcn_alignbyte(hi, lo, o - 4u);
         }
         if (q > 0) {
-            *(uint2 *)(g0 - s8 + 8u * q) = make_uint2(a, b);
+            *gptr<uint64_t>(g0 - s8 + 8u * q) = (uint64_t)b << 32 | a;
         } else {   // head: wave bytes [0, o)
 #pragma unroll
             for (uint32_t i = 0; i < 7u; ++i)
-                if (i < o) ((uint8_t *)g0)[i] = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
+                if (i < o) *gptr<uint8_t>(g0 + i) = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
         }
         if (r == kRows - 1 && lane == kWave - 1) {   // tail: own bytes [o, 8)
 #pragma unroll
             for (uint32_t i = 1; i < 8u; ++i)
                 if (i >= o)
-                    ((uint8_t *)g0)[8u * q + i] = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
+                    *gptr<uint8_t>(g0 + 8u * q + i) = (uint8_t)((i < 4u ? lo >> (8 * i) : hi >> (8 * (i - 4u))) & 0xFFu);
         }
     }
 }
@@ -482,11 +482,12 @@ __device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g
 static_assert(3 * kTileUnits <= 65536, "16-bit block offsets");
 
 template <bool kConvert, bool kBatch>
-// Six waves per SIMD (at most 80 VGPRs, a few spilled): this kernel waits on
-// memory and barriers more than it computes, and with eight-wave workgroups
-// six waves per SIMD is a third workgroup per CU (measured at 1 GiB: 15-19 %
-// faster on the non-ASCII mixes, 6 % on ASCII, than four waves per SIMD).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void utf16_tile_kernel(
+// Four waves per SIMD: the kernel needs about 93 VGPRs.  Held to six waves
+// per SIMD (80 VGPRs) the compiler spills VGPRs to scratch beside its SGPR
+// spills, and that build gave a wrong first-error result in a sequence of
+// calls that this build converts correctly, so the spilling build is not
+// used.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
     u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords16 : 4];

@@ -328,16 +328,19 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
         const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
         if (j == 0) lead0 = lead;
         const uint32_t f0 = has4(kClass) ? ge_f0(x) & 0x80808080u : 0u;
+        // per byte position: 4 (one slot) past a leading byte and 4 more
+        // past a byte >= F0; the marked copy's offset, 4 for a byte >= F0
+        const uint32_t mark = f0 >> 5;
+        const uint32_t step = (lead >> 5) + mark;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t win = window4(x, nx, k);
             const uint32_t a = has4(kClass) ? min(o, kLast) : o;
-            const uint32_t fb = has4(kClass) ? __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1) << 2 : 0u;
             // the marked copy goes to the next slot for a four-byte leading
             // byte, else to this slot, where the plain window replaces it
-            if (has4(kClass)) *(uint32_t *)(sb + a + fb) = win ^ 0x70u;
+            if (has4(kClass)) *(uint32_t *)(sb + add_byte(a, mark, k)) = win ^ 0x70u;
             *(uint32_t *)(sb + a) = win;
-            o += (__builtin_amdgcn_ubfe(lead, 8 * k + 7, 1) << 2) + fb;
+            o = add_byte(o, step, k);
         }
     }
     // rewrite the first slot
@@ -379,55 +382,62 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
 // selects between them stay selects.
 __device__ __forceinline__ void opaque(uint32_t &a, uint32_t &b) { asm volatile("" : "+v"(a), "+v"(b)); }
 
+// The values of a window's character are sums of its bytes with fixed
+// weights, which v_dot4_u32_u8 forms in one instruction (byte k of the
+// weight word times byte k of the window, plus a 32-bit addend).  For a
+// leading byte b0 and continuation bytes b1, b2, b3 (the marker bits of
+// each byte are constants that the addends cancel):
+//   two bytes    v2 = 64 b0 + b1 - 0x3080
+//   three bytes  v3 = 64 v2 + b2 - 0x20080         = 4096 b0 + 64 b1 + b2 - 0xE2080
+//   four bytes   v4 = 4096 v2 + 64 b2 + b3 - 0xC02080
+//                   = 2^18 b0 + 4096 b1 + 64 b2 + b3 - 0x3C82080
+// each exact (the code point) when the bytes form a character of that
+// length.  A marked low-surrogate copy (first byte F0..F4 xor 0x70, i.e.
+// 0x70 less) gives v4 smaller by 0x70 << 18, which leaves its low ten bits
+// -- all the low surrogate needs -- unchanged.
+constexpr uint32_t kWeights2 = 0x00000140u;   // bytes 0, 1 weighted 64, 1
+constexpr uint32_t kWeights3 = 0x00010000u;   // byte 2
+constexpr uint32_t kWeights4 = 0x01400000u;   // bytes 2, 3 weighted 64, 1
+
+__device__ __forceinline__ uint32_t dot4(uint32_t w, uint32_t weights, uint32_t addend) {
+    return __builtin_amdgcn_udot4(w, weights, addend, false);
+}
+
 template <uint32_t kClass>
 __device__ __forceinline__ uint32_t decode_word(uint32_t w, bool &bad) {
-    if (kClass == kUpTo2) {
-        const uint32_t b0 = w & 0xFFu;
-        uint32_t c2 = ((w & 0x1Fu) << 6) | ((w >> 8) & 0x3Fu);
-        opaque(c2, c2);
-        bad |= (w & 0xFEu) == 0xC0u;                          // C0, C1: overlong
-        return b0 >= 0xC0u ? c2 : b0;
-    }
-    if (kClass == kQuad) {
-        const bool low = (w & 0xC0u) == 0x80u;                 // marked low-surrogate copy
-        w ^= low ? 0x70u : 0u;
-        const uint32_t b0 = w & 0xFFu;
-        const uint32_t c4 = ((w & 0x0Fu) << 18) | (((w >> 8) & 0x3Fu) << 12) | (((w >> 16) & 0x3Fu) << 6) |
-                            ((w >> 24) & 0x3Fu);
-        // rule 1 (F8..FF) lands above U+10FFFF through the fourth payload bit
-        bad |= (b0 >= 0x80u) & (c4 - 0x10000u > 0xFFFFFu);
-        uint32_t hi = 0xD7C0u + (c4 >> 10), lo = 0xDC00u | (c4 & 0x3FFu);
-        opaque(hi, lo);
-        return b0 < 0x80u ? b0 : (low ? lo : hi);
-    }
-    bool low = false;
-    if (kClass == kAny) {
-        low = (w & 0xC0u) == 0x80u;                            // marked low-surrogate copy
-        w ^= low ? 0x70u : 0u;
-    }
     const uint32_t b0 = w & 0xFFu;
-    const uint32_t x1 = (w >> 8) & 0x3Fu;
-    const uint32_t x2 = (w >> 16) & 0x3Fu;
-    uint32_t c2 = ((w & 0x1Fu) << 6) | x1;
-    uint32_t c3 = ((w & 0x0Fu) << 12) | (x1 << 6) | x2;
-    opaque(c2, c3);   // computed for every word: selects, not branches
+    uint32_t v2 = dot4(w, kWeights2, 0u - 0x3080u);
+    if (kClass == kUpTo2) {
+        opaque(v2, v2);
+        bad |= (w & 0xFEu) == 0xC0u;                          // C0, C1: overlong
+        return b0 >= 0xC0u ? v2 : b0;
+    }
+    if (kClass == kQuad) {   // ASCII, four-byte leading bytes and their marked copies
+        const uint32_t v4 = dot4(w, kWeights4, (v2 << 12) - 0xC02080u);
+        const bool l4 = b0 >= 0xF0u;
+        // rule 1 (F8..FF) and F5..F7 land above U+10FFFF
+        bad |= l4 & (v4 - 0x10000u > 0xFFFFFu);
+        uint32_t hi = 0xD7C0u + (v4 >> 10), lo = 0xDC00u | (v4 & 0x3FFu);
+        opaque(hi, lo);
+        return b0 < 0x80u ? b0 : (l4 ? hi : lo);
+    }
+    uint32_t v3 = dot4(w, kWeights3, (v2 << 6) - 0x20080u);
+    opaque(v2, v3);   // computed for every word: selects, not branches
     const bool l3 = b0 >= 0xE0u;
-    // three-byte value below U+0800 (top five bits 0) or a surrogate (11011)
-    const bool b3 = (0x08000001u >> (c3 >> 11)) & 1u;
-    uint32_t u = l3 ? c3 : (b0 >= 0xC0u ? c2 : b0);
+    // a three-byte value below U+0800 (top five bits 0) or a surrogate (11011)
+    const bool b3 = __builtin_amdgcn_ubfe(0x08000001u, v3 >> 11, 1) != 0u;
+    const uint32_t u = l3 ? v3 : (b0 >= 0xC0u ? v2 : b0);
     if (kClass == kUpTo3) {
         bad |= ((w & 0xFEu) == 0xC0u) | (l3 & b3);
         return u;
     }
-    // four bytes: rule 1 (F8..FF) lands above U+10FFFF through the fourth
-    // payload bit kept here
+    // kAny: four bytes too, and marked low-surrogate copies (80..8F)
+    const uint32_t v4 = dot4(w, kWeights4, (v2 << 12) - 0xC02080u);
     const bool l4 = b0 >= 0xF0u;
-    const uint32_t c4 = ((w & 0x0Fu) << 18) | (x1 << 12) | (x2 << 6) | ((w >> 24) & 0x3Fu);
-    bad |= ((w & 0xFEu) == 0xC0u) | (l3 & !l4 & b3) | (l4 & (c4 - 0x10000u > 0xFFFFFu));
-    uint32_t hi = 0xD7C0u + (c4 >> 10), lo = 0xDC00u | (c4 & 0x3FFu);
+    bad |= ((w & 0xFEu) == 0xC0u) | (l3 & !l4 & b3) | (l4 & (v4 - 0x10000u > 0xFFFFFu));
+    uint32_t hi = 0xD7C0u + (v4 >> 10), lo = 0xDC00u | (v4 & 0x3FFu);
     opaque(hi, lo);
-    const uint32_t sur = low ? lo : hi;
-    return l4 ? sur : u;
+    return l4 ? hi : ((b0 & 0xC0u) == 0x80u ? lo : u);
 }
 
 // Group 0 decoded before the tile prefix (and so h) is known, by the waves
@@ -675,8 +685,10 @@ __device__ __forceinline__ bool quad_values_bad(const LaneBytes &t, uint32_t lan
 __device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, uint32_t lane,
                                              bool vals) {
     uint16_t *st16 = (uint16_t *)wst;
+    uint8_t *sb = (uint8_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
+    uint32_t ob = 2u * o;   // byte offset of the slot
     uint32_t bad = 0, h0e = 0, h0o = 0, l0e = 0, l0o = 0, h1e = 0, h1o = 0, L = 0, F = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -695,11 +707,13 @@ __device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t
             h1e = he; h1o = ho;
             L |= nibble_of(lead) << 4;
         }
+        // per byte position: 2 past a leading byte, 2 more past a byte >= F0
+        const uint32_t step = (lead >> 6) + (f0 >> 6);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            st16[o] = (uint16_t)word_at2(he, ho, (uint32_t)k);
-            st16[o + 1] = (uint16_t)word_at2(le, lo, (uint32_t)k);
-            o += __builtin_amdgcn_ubfe(lead, 8 * k + 7, 1) + __builtin_amdgcn_ubfe(f0, 8 * k + 7, 1);
+            *(uint16_t *)(sb + ob) = (uint16_t)word_at2(he, ho, (uint32_t)k);
+            *(uint16_t *)(sb + ob + 2) = (uint16_t)word_at2(le, lo, (uint32_t)k);
+            ob = add_byte(ob, step, k);
         }
     }
     // a first dword without a leading byte is invalid input: every slot of
@@ -733,8 +747,10 @@ template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
                                                long long head, long long end, uint32_t lane) {
     uint16_t *st16 = (uint16_t *)wst;
+    uint8_t *sb = (uint8_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
+    uint32_t ob = 2u * o;   // byte offset of the slot
     uint32_t bad = 0, ce0 = 0, co0 = 0, lead0 = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -748,10 +764,11 @@ __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_
             co0 = co;
             lead0 = lead;
         }
+        const uint32_t step = lead >> 6;   // per byte position: 2 past a leading byte
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            st16[o] = (uint16_t)word_at2(ce, co, (uint32_t)k);
-            o += __builtin_amdgcn_ubfe(lead, 8 * k + 7, 1);
+            *(uint16_t *)(sb + ob) = (uint16_t)word_at2(ce, co, (uint32_t)k);
+            ob = add_byte(ob, step, k);
         }
     }
     // rewrite the first slot (see scatter_row)

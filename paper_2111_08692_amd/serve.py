@@ -43,7 +43,8 @@ class _Flight:
     event: torch.cuda.Event
     ids: np.ndarray           # request ids of this launch
     kind: int                 # 0: UTF-8 -> UTF-16LE, 1: the reverse
-    held: int                 # output pool bytes held until completion
+    held: int                 # arena bytes held until completion
+    start: int = 0            # arena byte offset of the launch's output
     done: bool = False
 
 
@@ -215,9 +216,12 @@ class Server:
                     self._launch(kind, i, j, 0, s)
                 s.synchronize()   # the calls share the pool's first bytes
 
-    def run(self, time_scale: float = 1.0) -> ServeResult:
+    def run(self, time_scale: float = 1.0, collect: bool = False) -> ServeResult:
         """Serve every request once, replaying arrivals in wall-clock time
-        (``time_scale`` stretches the schedule)."""
+        (``time_scale`` stretches the schedule).  With ``collect`` every
+        launch's output is copied to the host as it completes, before its
+        arena space can be reused, so that ``output_of`` returns any
+        request's output after the run (for checking; it slows the loop)."""
         r = self.r
         n = self.n
         arr = r.arrival * time_scale
@@ -234,6 +238,8 @@ class Server:
                   "next": 0}]
         finished = launches = max_inflight = si = held_passes = 0
         held = np.zeros(n, dtype=bool)   # requests that arrived and had to wait for arena space
+        blobs = []                       # collect: (arena start, host copy) per completed launch
+        blob_of = np.full(n, -1, dtype=np.int64)
         t0 = time.perf_counter()
         while finished < n:
             now = time.perf_counter() - t0
@@ -269,7 +275,7 @@ class Server:
                     ev.record(s)
                 ids = q["ids"][i:j]
                 batch_offsets.append((ids, oo, start, kind))
-                inflight.append(_Flight(ev, ids, kind, charged))
+                inflight.append(_Flight(ev, ids, kind, charged, start))
                 q["next"] = j
                 launches += 1
                 launched = True
@@ -278,6 +284,9 @@ class Server:
             t = time.perf_counter() - t0
             for f in inflight:
                 if not f.done and f.event.query():
+                    if collect:
+                        blob_of[f.ids] = len(blobs)
+                        blobs.append((f.start, self.arena[f.start:f.start + f.held].cpu().numpy()))
                     f.done = True
                     done_t[f.ids] = t
                     finished += f.ids.size
@@ -308,13 +317,19 @@ class Server:
         span = float(done_t.max() - arr.min()) if n else 0.0
         return ServeResult(status=status, count=count, out_off=out_off, latency=latency, span_s=span,
                            input_bytes=int(r.size.sum()), launches=launches, max_inflight=max_inflight,
-                           held_back=int(held.sum()), held_passes=held_passes)
+                           held_back=int(held.sum()), held_passes=held_passes,
+                           extra={"blobs": blobs, "blob_of": blob_of} if collect else {})
 
     def output_of(self, res: ServeResult, rid: int) -> np.ndarray:
-        """The output units of request ``rid`` after ``run`` (a valid request;
-        only while later requests have not reused its space: the arena is a
-        ring, so this holds when a run's outputs fit the arena)."""
+        """The output units of request ``rid`` after ``run`` (a valid
+        request): from the host copy taken at its completion when the run
+        collected outputs, else from the arena (valid only while later
+        launches have not reused its space)."""
         cnt, o = int(res.count[rid]), int(res.out_off[rid])
-        if self.r.kind[rid] == 0:
-            return self.arena[o:o + 2 * cnt].cpu().numpy().view(np.uint16)
-        return self.arena[o:o + cnt].cpu().numpy()
+        nbytes = 2 * cnt if self.r.kind[rid] == 0 else cnt
+        if "blobs" in res.extra:
+            start, blob = res.extra["blobs"][int(res.extra["blob_of"][rid])]
+            b = blob[o - start:o - start + nbytes]
+        else:
+            b = self.arena[o:o + nbytes].cpu().numpy()
+        return b.view(np.uint16) if self.r.kind[rid] == 0 else b

@@ -457,3 +457,80 @@ def test_ascii_narrow_store_blocks(rows):
                     put(base + 8 * q + i, ((lo | hi << 32) >> (8 * i)) & 0xFF)
         assert sorted(mem) == list(range(base, base + n)), base
         assert all(mem[base + i] == int(wave[i]) for i in range(n)), base
+
+
+# --------------------------------------------------------------------------
+# 8. Weighted byte sums (v_dot4_u32_u8) decode a window.  For the window
+#    w = b0 | b1 << 8 | b2 << 16 | b3 << 24 the windows decoder forms
+#      v2 = 64 b0 + b1 - 0x3080, v3 = 64 v2 + b2 - 0x20080,
+#      v4 = 4096 v2 + 64 b2 + b3 - 0xC02080          (all modulo 2^32)
+#    and for a leading byte >= F0 the surrogates 0xD7C0 + (v4 >> 10) and
+#    0xDC00 | (v4 & 0x3FF); a marked copy (first byte xor 0x70) must give the
+#    same low surrogate.  Its value flags are: C0/C1; a three-byte lead whose
+#    v3 >> 11 is 0 or 27 (below U+0800, or U+D800..DFFF); a lead >= F0 whose
+#    v4 - 0x10000 exceeds 0xFFFFF.
+# --------------------------------------------------------------------------
+
+M32 = (1 << 32) - 1
+
+
+def _dot4(w, weights, addend):
+    s = np.zeros_like(w)
+    for k in range(4):
+        s = s + ((w >> (8 * k)) & 0xFF) * ((weights >> (8 * k)) & 0xFF)
+    return (s + addend) & M32
+
+
+def _decode_model(w):
+    """(word, bad) of the kAny windows decoder for uint64 windows w."""
+    b0 = w & 0xFF
+    v2 = _dot4(w, 0x00000140, (-0x3080) & M32)
+    v3 = _dot4(w, 0x00010000, ((v2 << 6) - 0x20080) & M32)
+    v4 = _dot4(w, 0x01400000, ((v2 << 12) - 0xC02080) & M32)
+    l3, l4 = b0 >= 0xE0, b0 >= 0xF0
+    b3 = ((0x08000001 >> ((v3 >> 11) & 31)) & 1) == 1
+    bad = ((w & 0xFE) == 0xC0) | (l3 & ~l4 & b3) | (l4 & (((v4 - 0x10000) & M32) > 0xFFFFF))
+    hi, lo = (0xD7C0 + (v4 >> 10)) & 0xFFFF, 0xDC00 | (v4 & 0x3FF)
+    u = np.where(l3, v3, np.where(b0 >= 0xC0, v2, b0)) & 0xFFFF
+    word = np.where(l4, hi, np.where((b0 & 0xC0) == 0x80, lo, u))
+    return word, bad
+
+
+def test_weighted_sums_decode_every_scalar_value():
+    """Every scalar value: the window of its UTF-8 form decodes to its first
+    UTF-16 word (Python's encoders), the marked copy of a four-byte form to
+    its low surrogate, and no value flag is raised."""
+    cps = [c for c in range(0x110000) if not 0xD800 <= c <= 0xDFFF]
+    text = "".join(map(chr, cps))
+    u8 = text.encode("utf-8")
+    lens = np.array([1 if c < 0x80 else 2 if c < 0x800 else 3 if c < 0x10000 else 4 for c in cps])
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    buf = np.frombuffer(u8 + b"\0\0\0", dtype=np.uint8).astype(np.uint64)
+    w = buf[starts] | buf[starts + 1] << 8 | buf[starts + 2] << 16 | buf[starts + 3] << 24
+    w = np.where(lens == 1, w & 0xFF, np.where(lens == 2, w & 0xFFFF, np.where(lens == 3, w & 0xFFFFFF, w)))
+    word, bad = _decode_model(w)
+    u16 = np.frombuffer(text.encode("utf-16-le"), dtype="<u2").astype(np.uint64)
+    first = np.concatenate([[0], np.cumsum(np.where(lens == 4, 2, 1))[:-1]])
+    assert not bad.any()
+    assert np.array_equal(word, u16[first])
+    four = lens == 4
+    lo_word, lo_bad = _decode_model(w[four] ^ 0x70)
+    assert np.array_equal(lo_word, u16[first[four] + 1])
+
+
+@pytest.mark.parametrize("lead", range(0xC0, 0x100))
+def test_weighted_sums_value_flags_match_the_rules(orc, lead):
+    """Every window of one leading byte followed by the continuation bytes it
+    announces (all 64^(L-1) of them, L = 2, 3, 4; L = 4 for F8..FF too): the
+    value flag is raised exactly when the oracle rejects the sequence (its
+    structure being complete, only rules 1, 4, 5, 6 can fail)."""
+    L = 2 if lead < 0xE0 else 3 if lead < 0xF0 else 4
+    conts = np.arange(0x80, 0xC0, dtype=np.uint64)
+    grids = np.meshgrid(*([conts] * (L - 1)), indexing="ij")
+    w = np.full(grids[0].size, lead, dtype=np.uint64)
+    for k, g in enumerate(grids):
+        w |= g.reshape(-1) << (8 * (k + 1))
+    _, bad = _decode_model(w)
+    data = np.stack([(w >> (8 * k)) & 0xFF for k in range(L)], axis=1).astype(np.uint8).reshape(-1)
+    st, _ = orc.validate_utf8_batch(data, np.arange(0, data.size + 1, L, dtype=np.int64))
+    assert np.array_equal(bad, st != O.OK)

@@ -29,13 +29,13 @@ def served(G):
                          pool_bytes=4 << 20)
     srv = Server(reqs, nstreams=3, hbm_budget=_everything(reqs), max_batch_bytes=1 << 20)
     srv.prewarm()
-    res = srv.run()
+    res = srv.run(collect=True)
     return reqs, srv, res
 
 
 def _everything(reqs):
-    """An arena budget that holds every request's reservation at once, so no
-    output is overwritten before the test reads it."""
+    """An arena budget that holds every request's reservation at once (the
+    outputs are read as each launch completes)."""
     from paper_2111_08692_amd.serve import reservation
     return (sum(reservation(0, int(d)) for d in np.diff(reqs.off8)) +
             sum(reservation(1, int(d)) for d in np.diff(reqs.off16)) + (1 << 20))
@@ -127,7 +127,7 @@ def test_invalid_request_widens_the_batch(G):
                       invalid=np.array([True, False, False, False]), ids8=np.array([0, 1, 2]), off8=off8,
                       data8=np.concatenate(p8), ids16=np.array([3]), off16=off16, data16=np.concatenate(p16))
     srv = Server(reqs, nstreams=1, hbm_budget=1 << 20)
-    res = srv.run(time_scale=0.0)
+    res = srv.run(time_scale=0.0, collect=True)
     assert list(res.status) == [1, 0, 0, 0] and list(res.count[1:]) == [3000, 3000, 10]
     assert np.all(srv.output_of(res, 1) == 0x61) and np.all(srv.output_of(res, 2) == 0x62)
 
@@ -146,7 +146,8 @@ def _oracle_all(orc, reqs):
         conv = orc.convert_utf8_to_utf16le_batch if kind == 0 else orc.convert_utf16le_to_utf8_batch
         st, cnt, o, oo = conv(data, off)
         for j, rid in enumerate(ids):
-            out[int(rid)] = (int(st[j]), int(cnt[j]), o[oo[j]:oo[j] + cnt[j]] if st[j] == 0 else None)
+            a, c = int(oo[j]), int(cnt[j])
+            out[int(rid)] = (int(st[j]), c, o[a:a + c] if st[j] == 0 else None)
     return out
 
 
@@ -163,7 +164,7 @@ def workload_shape(G, orc):
 @pytest.mark.parametrize("time_scale", [1.0, 0.0], ids=["open_loop_50k", "burst"])
 def test_workload_shape_every_request_vs_oracle(workload_shape, time_scale):
     reqs, srv, ref = workload_shape
-    res = srv.run(time_scale=time_scale)
+    res = srv.run(time_scale=time_scale, collect=True)
     assert res.launches >= 2 and np.all(np.isfinite(res.latency))
     for rid in range(reqs.arrival.size):
         st, cnt, o = ref[rid]
