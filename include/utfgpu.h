@@ -209,6 +209,30 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
                                             int64_t *out_offsets, utf_result *results, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Allocation-free conversion                                             */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * same work and results as convert_utf8_to_utf16le_async, with the look-back
+ * status words and control block in a fixed array of device memory that the
+ * library holds on each device until the process ends (16 MiB + 256 bytes)
+ * instead of a per-stream workspace.  The call allocates nothing; its first
+ * call on a device looks the array's address up and initialises it with a
+ * kernel on `stream`.  At most UTF_NOALLOC_MAX_TILES tiles: with the shipped
+ * geometry table, inputs of up to 2 GiB - 64 bytes; a larger input returns
+ * UTF_ERR_TOO_BIG and enqueues nothing.  Every call on a device shares that
+ * device's array: calls that overlap on one device (different streams, or
+ * different host threads, without ordering between them) race and give
+ * undefined results; calls ordered on one stream are safe.  Arguments and
+ * return value as convert_utf8_to_utf16le_async.
+ */
+#define UTF_NOALLOC_MAX_TILES 65536
+int32_t convert_utf8_to_utf16le_noalloc_async(const uint8_t *in, uint64_t n, uint16_t *out, uint64_t out_cap,
+                                              utf_result *result, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Library state                                                          */
 /* ---------------------------------------------------------------------- */
 

@@ -72,6 +72,7 @@ EXPORTS = (
     "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async", "convert_utf16le_to_utf8_batch_async",
     "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
     "utfgpu_geometry_count", "utfgpu_geometry", "utfgpu_set_geometry", "utfgpu_get_geometry", "utfgpu_size_class",
+    "convert_utf8_to_utf16le_noalloc_async",
 )
 
 
@@ -104,6 +105,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "utfgpu_set_geometry": ([I32, I32, I32], I32),
         "utfgpu_get_geometry": ([I32, I32], I32),
         "utfgpu_size_class": ([U64], I32),
+        "convert_utf8_to_utf16le_noalloc_async": ([P, U64, P, U64, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -290,6 +292,17 @@ def convert_utf8_to_utf16le_async(data, out, result, out_cap=None, stream=None) 
     cap = out.numel() if out_cap is None else int(out_cap)
     return int(load().convert_utf8_to_utf16le_async(_ptr(data), data.numel(), _ptr(out), cap,
                                                  result.data_ptr(), _stream(stream)))
+
+
+def convert_utf8_to_utf16le_noalloc_async(data, out, result, out_cap=None, stream=None) -> int:
+    """The allocation-free form of ``convert_utf8_to_utf16le_async`` (one
+    fixed device array per device, shared by every call: calls that overlap
+    on one device race)."""
+    _dev(data, 1, "data")
+    _dev(out, 2, "out")
+    cap = out.numel() if out_cap is None else int(out_cap)
+    return int(load().convert_utf8_to_utf16le_noalloc_async(_ptr(data), data.numel(), _ptr(out), cap,
+                                                         result.data_ptr(), _stream(stream)))
 
 
 def convert_utf16le_to_utf8_async(data, out, result, out_cap=None, stream=None) -> int:

@@ -362,6 +362,48 @@ int32_t enqueue_utf16(bool convert, const uint16_t *in, u64 m, uint8_t *out, u64
     return UTF_OK;
 }
 
+// ---- the allocation-free entry point --------------------------------------
+// Its workspace is a fixed array of device memory: the control block in
+// the first 256 bytes, then one status word per tile, kStatusStride words
+// apart.  Each device holds its own copy until the process ends.  In host
+// code `scratch` only names the symbol; the device address of each
+// device's copy comes from hipGetSymbolAddress and is kept per device.
+constexpr u64 kNoAllocTiles = 65536;
+constexpr u64 kNoAllocCtrlWords = 32;
+static_assert(sizeof(Ctrl) <= kNoAllocCtrlWords * sizeof(u64), "control block fits its slot");
+__device__ __align__(256) u64 scratch[kNoAllocCtrlWords + kNoAllocTiles * kStatusStride];
+
+constexpr int kMaxDevices = 64;
+struct NoAllocState {
+    bool ready = false;
+    u64 *ptr = nullptr;   // device address of this device's scratch
+};
+NoAllocState g_noalloc[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+// This device's scratch, set up on the first call made on it: its address,
+// then its control block and status words initialised on `s`.
+hipError_t noalloc_scratch(hipStream_t s, u64 **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocState &st = g_noalloc[dev];
+    if (!st.ready) {
+        u64 *ptr = nullptr;
+        if ((e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        if ((e = base::launch_ctrl_init(reinterpret_cast<Ctrl *>(ptr), ptr + kNoAllocCtrlWords, kNoAllocTiles,
+                                        epoch_period(), s)) != hipSuccess)
+            return e;
+        st.ptr = ptr;
+        st.ready = true;
+    }
+    *out = st.ptr;
+    return hipSuccess;
+}
+
 utf_result read_result(Workspace *w, hipStream_t s) {
     if (hipMemcpyAsync(w->hres, w->dres, sizeof(DevResult), hipMemcpyDeviceToHost, s) != hipSuccess)
         return mk(UTF_ERR_HIP, 0);
@@ -587,6 +629,27 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (g.utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
                            reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
                            w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
+        return UTF_ERR_HIP;
+    return UTF_OK;
+}
+
+int32_t convert_utf8_to_utf16le_noalloc_async(const uint8_t *in, uint64_t n, uint16_t *out, uint64_t out_cap,
+                                              utf_result *result, void *stream) {
+    int32_t c = check8(in, n);
+    if (c != UTF_OK) return c;
+    if (!result || (!out && out_cap > 0)) return UTF_ERR_NULL;
+    if (reinterpret_cast<uintptr_t>(out) & 1u) return UTF_ERR_ALIGN;
+    hipStream_t s = as_stream(stream);
+    DevResult *r = reinterpret_cast<DevResult *>(result);
+    if (n == 0) return base::launch_set_result(r, UTF_OK, 0, s) == hipSuccess ? UTF_OK : UTF_ERR_HIP;
+    const long long head = head_bytes(in);
+    const Geometry &g = geometry_for(UTF_OP_CONVERT_UTF8, n);
+    const u64 nt = g.utf8_tiles_for(head, (long long)n);
+    if (nt > kNoAllocTiles) return UTF_ERR_TOO_BIG;
+    u64 *p = nullptr;
+    if (noalloc_scratch(s, &p) != hipSuccess) return UTF_ERR_HIP;
+    if (g.utf8_tiles(true, frame_of(in), head, (long long)n, out, out_cap, p + kNoAllocCtrlWords,
+                     reinterpret_cast<Ctrl *>(p), r, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
