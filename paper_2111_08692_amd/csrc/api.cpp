@@ -182,7 +182,6 @@ struct Workspace {
     u64 *status = nullptr;       // device tile status words
     u64 status_cap = 0;
     // batched calls
-    uint32_t *bad = nullptr;        // offsets check flag
     uint32_t *starts = nullptr;     // string-start bitmap (all zero between calls)
     u64 starts_words = 0;
     uint16_t *blockoff = nullptr;   // per 64-byte block: output offset inside its tile
@@ -206,7 +205,6 @@ void free_ws(Workspace *w) {
     if (w->partials) (void)hipFree(w->partials);
     if (w->hres) (void)hipHostFree(w->hres);
     if (w->hlen) (void)hipHostFree(w->hlen);
-    if (w->bad) (void)hipFree(w->bad);
     if (w->starts) (void)hipFree(w->starts);
     if (w->blockoff) (void)hipFree(w->blockoff);
     if (w->tilepre) (void)hipFree(w->tilepre);
@@ -288,9 +286,6 @@ hipError_t grow(T **p, u64 *cap, u64 need, int fill, hipStream_t s) {
 // cover both directions).
 hipError_t get_batch(Workspace *w, u64 ntiles, u64 tile_units, u64 waves, u64 k, hipStream_t s) {
     hipError_t e;
-    if (!w->bad) {
-        if ((e = hipMalloc(&w->bad, sizeof(uint32_t))) != hipSuccess) return e;
-    }
     const u64 positions = ntiles * tile_units + 128;   // every tile and the chunk past the last
     if ((e = grow(&w->starts, &w->starts_words, positions / 32 + 2, 0, s)) != hipSuccess) return e;
     if ((e = grow(&w->blockoff, &w->blockoff_cap, positions / 32 + 2, 0, s)) != hipSuccess) return e;
@@ -602,7 +597,7 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     if (get_batch(w, nt, g.tile_bytes(), g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                          w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
+                          w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
@@ -628,7 +623,7 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (get_batch(w, nt, g.tile_bytes() / 2, g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
                            reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                           w->blockoff, w->tilepre, w->serr, w->bad, w->wavestr, s) != hipSuccess)
+                           w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr, s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }

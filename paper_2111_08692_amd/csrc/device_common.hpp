@@ -98,9 +98,12 @@ struct DevResult {
 // however many calls (eager or replayed from a captured graph) ran.
 struct Ctrl {
     u64 err;        // min over (position << 4 | kind); ~0 when no error
-    u64 pad0[7];
+    u64 ticket;     // batched calls: the next tile index to hand out
+    u64 pad0[6];
     u64 total;      // output units of the whole call (written by the last tile)
-    u64 pad1[7];
+    uint32_t bad;   // batched calls: the offsets are not a partition of the input
+    uint32_t pad_b;
+    u64 pad1[6];
     u64 epoch;      // tag of the status words of the current call
     u64 period;     // at most 2^22 (the epoch field of a status word)
     u64 *status;    // the workspace's status words, kStatusStride words apart
@@ -220,6 +223,23 @@ __device__ __forceinline__ uint32_t keep_range(uint32_t x, long long p, long lon
     if (a >= 4) return 0u;
     if (a > 0) m &= ~((1u << (8 * a)) - 1u);
     return x & m;
+}
+
+// ------------------------------------------------------------------------
+// Tile tickets (batched calls)
+// ------------------------------------------------------------------------
+// Batched calls take each workgroup's tile index from a counter in the
+// control block, in the order the workgroups start, instead of using the
+// workgroup index: every tile before a running tile then belongs to a
+// workgroup that has already started, so a look-back never waits on a
+// workgroup the hardware has not placed -- which, with several batched
+// kernels in flight on other streams, can happen for a while.  (Not used for
+// single-buffer calls: the same-address atomic costs them a few percent.)
+// Run by the whole workgroup; `slot` is a __shared__ word.
+__device__ __forceinline__ u64 take_ticket(Ctrl *ctrl, uint32_t *slot, uint32_t tid) {
+    if (tid == 0) *slot = (uint32_t)__hip_atomic_fetch_add(&ctrl->ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return (u64)__builtin_amdgcn_readfirstlane(*slot);   // fewer than 2^32 tiles
 }
 
 // ------------------------------------------------------------------------

@@ -497,7 +497,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
-    const u64 tile = blockIdx.x;
+    __shared__ uint32_t s_ticket;
+    const u64 tile = kBatch ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
     const long long end = head + m;
     const long long wbase = (long long)tile * kTileUnits + (long long)wave * kWaveUnits;
 

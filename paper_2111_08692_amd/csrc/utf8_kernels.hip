@@ -1041,7 +1041,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
     const long long end = head + n;
-    const u64 tile = blockIdx.x;
+    __shared__ uint32_t s_ticket;
+    const u64 tile = kBatch ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
     const long long wbase = (long long)tile * kTileBytes + (long long)wave * kWaveBytes;
     LaneBytes t;
     issue_span(frame, end, wbase, lane, t);
@@ -1280,6 +1281,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(Ctrl *ctrl, DevResult 
     result->pad = 0;
     st_agent(&ctrl->err, ~0ull);
     st_agent(&ctrl->total, 0);
+    st_agent(&ctrl->ticket, 0);
+    ctrl->bad = 0;
     st_agent(&ctrl->epoch, wrap ? 1 : next);
 }
 
@@ -1290,6 +1293,8 @@ __global__ __launch_bounds__(kBlock) void ctrl_init_kernel(Ctrl *ctrl, u64 *stat
     if (blockIdx.x == 0 && tid == 0) {
         ctrl->err = ~0ull;
         ctrl->total = 0;
+        ctrl->ticket = 0;
+        ctrl->bad = 0;
         ctrl->epoch = 1;
         ctrl->period = period;
         ctrl->status = status;
@@ -1341,12 +1346,21 @@ hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head,
 // ------------------------------------------------------------------------
 // Batched UTF-8 -> UTF-16LE
 // ------------------------------------------------------------------------
-// Marks the first byte of every non-empty string in the start bitmap and
-// checks the offsets (0 = offsets[0] <= ... <= offsets[k] = n); a bad array
-// sets `bad` and marks nothing for the strings it concerns.
+// Thread i <= k marks the first byte of string i (when non-empty) in the
+// start bitmap and checks the offsets (0 = offsets[0] <= ... <= offsets[k]
+// = n); a bad array sets `bad` (a word of the control block, zero between
+// calls) and marks nothing for the strings it concerns.  Thread w <= nspans
+// records the string owning the first position of wave span w (`span`
+// units, frame coordinates), so that an error's owner is found among the
+// few strings near its wave.  One launch does both.
 __global__ void batch_prep_kernel(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
-                                  uint32_t *bad) {
+                                  uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans) {
     const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nspans) {
+        long long p = (long long)i * span - head;
+        p = p < 0 ? 0 : (p >= n ? n - 1 : p);
+        wavestr[i] = (uint32_t)owner_string(offsets, 0, k, p);
+    }
     if (i > k) return;
     const int64_t a = offsets[i];
     if (i == 0 && a != 0) atomicOr(bad, 1u);
@@ -1418,31 +1432,14 @@ __global__ void batch_post_kernel(const uint8_t *frame, long long head, long lon
     }
 }
 
-__global__ void clear_u32_kernel(uint32_t *p) {
-    if (threadIdx.x == 0) *p = 0;
-}
-
-// The string owning the first position of every wave span (`span` units,
-// frame coordinates), and of the end: lets an error's owner be found among
-// the few strings near its wave.
-__global__ void batch_index_kernel(const int64_t *offsets, u64 k, long long head, long long n, long long span,
-                                   uint32_t *wavestr, u64 nspans) {
-    const u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w > nspans) return;
-    long long p = (long long)w * span - head;
-    p = p < 0 ? 0 : (p >= n ? n - 1 : p);
-    wavestr[w] = (uint32_t)owner_string(offsets, 0, k, p);
-}
-
-// Clear the offsets flag, mark the string starts and index the wave spans
-// (both directions).
+// Mark the string starts and index the wave spans (both directions); the
+// offsets flag is cleared by the finalize kernel of the previous call.
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
                              uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream) {
-    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
-    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, bad);
-    hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad);
-    const unsigned ig = (unsigned)((nspans + 1 + pb - 1) / pb);
-    hipLaunchKernelGGL(batch_index_kernel, dim3(ig), dim3(pb), 0, stream, offsets, k, head, n, span, wavestr, nspans);
+    const u64 threads = (k > nspans ? k : nspans) + 1;
+    const unsigned pb = 256, pg = (unsigned)((threads + pb - 1) / pb);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad, span,
+                       wavestr, nspans);
     return hipGetLastError();
 }
 
