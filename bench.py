@@ -315,8 +315,9 @@ def serve_leg(reqs, small, aux):
     """The serving workload: open-loop Poisson arrivals at 50 000 requests/s,
     log-normal sizes (median 32 KiB, sigma ln(2^18)/6, 64 B..16 MiB), 50/50
     directions, 0.5% invalid; replayed in wall-clock time, then all at once
-    (saturation); then the open-loop replay again with the geometry tuner's
-    table for the batched calls (tuned on the 1 MiB mixed-script text)."""
+    (saturation); then both again with the tuner's geometry and schedule
+    tables for the batched calls (tuned on the 1 MiB mixed-script text, four
+    concurrent calls per timed round)."""
     from paper_2111_08692_amd.serve import Server
     import torch
     import paper_2111_08692_amd as G
@@ -375,42 +376,47 @@ def serve_leg(reqs, small, aux):
                              "(open loop), log-normal sizes median 32 KiB sigma 2.08 in 64 B..16 MiB, 50/50 "
                              "directions, 0.5% invalid; each direction batched per pass, 4 streams, one output arena "
                              "sized from free HBM (8 GiB budget), every stream's workspace pre-sized before timing")
-    # the same, with the batched calls' geometry tuned on mixed-script text
+    # the same, with the batched calls' geometry and scan schedule tuned on
+    # mixed-script text, four calls at a time on four streams as the server
+    # runs them
     from paper_2111_08692_amd import tune
     try:
         tune.tune(small.data, ops=("convert_utf8_to_utf16le_batch", "convert_utf16le_to_utf8_batch"),
                   sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24), min_ms=1.0, reps=3,
-                  string_bytes=32768)
+                  string_bytes=32768, concurrency=4)
         srv.prewarm()
         srv.run(time_scale=0.0)
         res = srv.run(time_scale=1.0)
         assert np.all(res.status[~reqs.invalid] == 0), "valid request failed"
         aux["serve_50k_rps_tuned_p50_us"] = round(res.percentile_us(50), 1)
         aux["serve_50k_rps_tuned_p99_us"] = round(res.percentile_us(99), 1)
+        res = srv.run(time_scale=0.0)
+        assert np.all(res.status[~reqs.invalid] == 0), "valid request failed"
+        aux["serve_burst_tuned_GBps"] = round(res.gbps, 2)
     finally:
         tune.reset()
 
 
 def tune_leg(small, aux):
-    """The geometry tuner on the 1 MiB mixed-script text, at four input
-    sizes: the geometry it picks, and its speed-up over geometry 0 and over
-    the library's shipped table.  The result is not installed (the other
-    legs run the shipped table)."""
+    """The tuner on the 1 MiB mixed-script text, at four input sizes: the
+    (geometry, scan schedule) pair it picks, and its speed-up over geometry 0
+    in block order and over the library's shipped table.  The result is not
+    installed (the other legs run the shipped table)."""
     from paper_2111_08692_amd import tune
     t0 = time.time()
     res = tune.tune(small.data, ops=("convert_utf8_to_utf16le", "convert_utf16le_to_utf8",
                                      "convert_utf8_to_utf16le_batch", "convert_utf16le_to_utf8_batch"),
                     sizes=(1 << 16, 1 << 20, 1 << 24, 1 << 28), min_ms=2.0, reps=3, install=False)
-    names = res["geometries"]
+    names = res["candidates"]   # "<geometry>/<schedule>", index 0 = geometry 0 in block order
     ops = {}
     for op, rows in res["measured"].items():
-        ops[op] = {str(r["bytes"]): {"geometry": r["choice"], "shipped": r["before"], "g0_us": r["us"][0],
+        ops[op] = {str(r["bytes"]): {"choice": r["choice"], "shipped": r["before"], "g0_us": r["us"][0],
                                      "speedup": round(r["us"][0] / r["us"][names.index(r["choice"])], 3),
                                      "speedup_vs_shipped": round(r["us"][names.index(r["before"])]
                                                                  / r["us"][names.index(r["choice"])], 3)}
                    for r in rows}
     aux["autotune"] = {"sample": "1 MiB mixed-script text, repeated; batched calls in strings of about 4 KiB",
-                       "geometries": names, "seconds": round(time.time() - t0, 1), "ops": ops}
+                       "candidates": names, "seconds": round(time.time() - t0, 1), "ops": ops}
 
 
 def host_leg(bufs, aux):

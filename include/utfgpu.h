@@ -76,7 +76,7 @@ enum {
     UTF_ERR_TOO_BIG = -3,
     UTF_ERR_HIP = -4,
     UTF_ERR_OFFSETS = -5,     /* batched calls: offsets are not a partition of the input */
-    UTF_ERR_ARG = -6          /* tuning calls: operation, size class or geometry out of range */
+    UTF_ERR_ARG = -6          /* tuning calls: operation, size class, geometry or schedule out of range */
 };
 
 /* Largest supported input: 2^40 - 1 UTF-8 bytes, 2^38 - 1 UTF-16 words. */
@@ -300,7 +300,51 @@ int32_t utfgpu_get_geometry(int32_t op, int32_t size_class);
 /* The size class of an input of `bytes` bytes. */
 int32_t utfgpu_size_class(uint64_t bytes);
 
-/* Library version string, e.g. "utfgpu 0.1 gfx950". */
+/* ---------------------------------------------------------------------- */
+/* Scan schedule and its tuning table                                     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * The validate and convert kernels find each tile's output offset with a
+ * single-pass scan over the tiles (each tile publishes its total and reads
+ * its predecessors' totals and prefixes: the decoupled look-back, the
+ * device-wide form of the output-offset computation that the paper's
+ * sequential loop carries from block to block, Section 4).  The schedule is
+ * the order in which workgroups take tiles:
+ *   UTF_SCHEDULE_BLOCK   tile = workgroup index (no shared counter);
+ *   UTF_SCHEDULE_TICKET  each workgroup takes the next index of a per-call
+ *                        counter when it starts, so every tile before a
+ *                        running tile belongs to a workgroup that has
+ *                        already started and no look-back ever waits on a
+ *                        workgroup the hardware has not placed (which
+ *                        happens while look-back kernels of other streams
+ *                        fill the device).
+ * Both compute the same results; tickets cost one atomic round trip before
+ * each tile's first load.  Validation has no scan: the entries of the two
+ * validate operations are kept but do not change what runs.  A process-wide table (operation, size class, as
+ * for the geometry) picks the schedule per call; the shipped default is
+ * UTF_SCHEDULE_BLOCK everywhere (faster on MI355X alone and, with the
+ * shipped geometries, for four concurrent serving streams).  The
+ * environment variable UTFGPU_SCHEDULE, set to a schedule index before the
+ * first call, overrides the table for the whole process.  Host state: no
+ * GPU needed, any thread, effective from the next call.
+ */
+enum {
+    UTF_SCHEDULE_BLOCK = 0,
+    UTF_SCHEDULE_TICKET = 1,
+    UTF_SCHEDULE_COUNT = 2
+};
+
+/* Make calls of operation `op` whose input falls in `size_class` use scan
+ * schedule `schedule` (-1 restores the shipped default).  UTF_OK or
+ * UTF_ERR_ARG. */
+int32_t utfgpu_set_schedule(int32_t op, int32_t size_class, int32_t schedule);
+
+/* The schedule such a call uses now (UTFGPU_SCHEDULE included), or
+ * UTF_ERR_ARG. */
+int32_t utfgpu_get_schedule(int32_t op, int32_t size_class);
+
+/* Library version string, e.g. "utfgpu 0.2 gfx950". */
 const char *utfgpu_version(void);
 
 /* Input bytes one workgroup of the validate/convert kernels covers in the

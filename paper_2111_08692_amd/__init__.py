@@ -56,6 +56,11 @@ OP_BATCH_UTF16LE = 5
 OP_COUNT = 6
 SIZE_CLASSES = 64
 
+# scan schedules (order in which workgroups take tiles)
+SCHEDULE_BLOCK = 0
+SCHEDULE_TICKET = 1
+SCHEDULE_NAMES = ("block", "ticket")
+
 STATUS_NAMES = {
     OK: "OK", TOO_SHORT: "TOO_SHORT", TOO_LONG: "TOO_LONG", OVERLONG: "OVERLONG",
     TOO_LARGE: "TOO_LARGE", SURROGATE: "SURROGATE", HEADER_BITS: "HEADER_BITS",
@@ -72,6 +77,7 @@ EXPORTS = (
     "convert_utf16le_to_utf8_async", "convert_utf8_to_utf16le_batch_async", "convert_utf16le_to_utf8_batch_async",
     "utfgpu_release_workspace", "utfgpu_version", "utfgpu_tile_bytes",
     "utfgpu_geometry_count", "utfgpu_geometry", "utfgpu_set_geometry", "utfgpu_get_geometry", "utfgpu_size_class",
+    "utfgpu_set_schedule", "utfgpu_get_schedule",
     "convert_utf8_to_utf16le_noalloc_async",
 )
 
@@ -105,6 +111,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "utfgpu_set_geometry": ([I32, I32, I32], I32),
         "utfgpu_get_geometry": ([I32, I32], I32),
         "utfgpu_size_class": ([U64], I32),
+        "utfgpu_set_schedule": ([I32, I32, I32], I32),
+        "utfgpu_get_schedule": ([I32, I32], I32),
         "convert_utf8_to_utf16le_noalloc_async": ([P, U64, P, U64, P, P], I32),
     }
     for name, (args, res) in sig.items():
@@ -168,6 +176,17 @@ def set_geometry(op: int, size_class: int, g: int) -> int:
 
 def get_geometry(op: int, size_class: int) -> int:
     return int(load().utfgpu_get_geometry(int(op), int(size_class)))
+
+
+def set_schedule(op: int, size_class: int, schedule: int) -> int:
+    """Calls of ``op`` whose input falls in ``size_class`` use scan schedule
+    ``schedule`` (SCHEDULE_BLOCK or SCHEDULE_TICKET; -1: the default).
+    Returns the C status."""
+    return int(load().utfgpu_set_schedule(int(op), int(size_class), int(schedule)))
+
+
+def get_schedule(op: int, size_class: int) -> int:
+    return int(load().utfgpu_get_schedule(int(op), int(size_class)))
 
 
 def size_class(nbytes: int) -> int:

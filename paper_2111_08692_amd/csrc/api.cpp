@@ -18,32 +18,34 @@
 // The launchers of every compiled tile geometry (C++ linkage; one build of
 // the kernel files per entry of geometries.def).
 #define UTF_GEOMETRY(NS, WAVES, ROWS)                                                                             \
-    namespace utfgpu {                                                                                           \
-    namespace NS {                                                                                               \
-    u64 build_tile_bytes();                                                                                      \
-    u64 utf8_tiles_for(long long head, long long n);                                                             \
-    u64 utf16_tiles_for(long long head, long long m);                                                            \
-    hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out, \
-                                 u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);   \
-    hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out, \
-                                  u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream);  \
+    namespace utfgpu {                                                                                            \
+    namespace NS {                                                                                                \
+    u64 build_tile_bytes();                                                                                       \
+    u64 utf8_tiles_for(long long head, long long n);                                                              \
+    u64 utf16_tiles_for(long long head, long long m);                                                             \
+    hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,  \
+                                 u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, int schedule,           \
+                                 hipStream_t stream);                                                             \
+    hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,  \
+                                  u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, int schedule,          \
+                                  hipStream_t stream);                                                            \
     hipError_t launch_utf16_length(const uint8_t *frame, long long head, long long n, u64 *partials, Ctrl *ctrl,  \
-                                   u64 *result, hipStream_t stream);                                             \
+                                   u64 *result, hipStream_t stream);                                              \
     hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,   \
-                                  u64 *result, hipStream_t stream);                                              \
-    hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);                   \
-    hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);                                                \
+                                  u64 *result, hipStream_t stream);                                               \
+    hipError_t launch_set_result(DevResult *r, int32_t status, u64 count, hipStream_t stream);                    \
+    hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);                                                 \
     hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets,       \
-                                 u64 k, uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,    \
-                                 u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,           \
-                                 uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr,  \
-                                 hipStream_t stream);                                                            \
+                                 u64 k, uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
+                                 u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,            \
+                                 uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr,   \
+                                 int schedule, hipStream_t stream);                                               \
     hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets,      \
-                                  u64 k, uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,    \
-                                  u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,          \
-                                  uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad,                    \
-                                  uint32_t *wavestr, hipStream_t stream);                                        \
-    }                                                                                                            \
+                                  u64 k, uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
+                                  u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,           \
+                                  uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad,                     \
+                                  uint32_t *wavestr, int schedule, hipStream_t stream);                           \
+    }                                                                                                             \
     }
 #include "geometries.def"
 #undef UTF_GEOMETRY
@@ -140,6 +142,42 @@ const Geometry &geometry_for(int op, u64 bytes) {
     const int f = forced_geometry();
     if (f >= 0) return kGeometries[f];
     return kGeometries[table_geometry(op, size_class(bytes))];
+}
+
+// Scan schedule table, laid out like the geometry table (1 + the schedule,
+// 0: the shipped default).  The schedule is the order in which the tile
+// kernels' workgroups take their tiles: UTF_SCHEDULE_BLOCK, tile = workgroup
+// index; UTF_SCHEDULE_TICKET, the next index of a per-call counter taken when
+// the workgroup starts.  Both compute the same results.  The shipped default
+// is block order everywhere: on MI355X tickets made a 100 000-string batched
+// call 9 % (UTF-8) and 16 % (UTF-16) slower, a burst of serving requests on
+// four streams 10 % slower with the shipped geometries, and single-buffer
+// ASCII conversions 6.5 % slower (the counter's round trip precedes each
+// tile's first load).  Ticket order is for concurrency the geometry table
+// does not cover: it keeps a burst with 8 x 4 batched UTF-16 calls at
+// 790 GB/s where block order halves it.
+constexpr int kNumSchedules = UTF_SCHEDULE_COUNT;
+static_assert(kScheduleTicket == UTF_SCHEDULE_TICKET, "schedule index");
+std::atomic<uint8_t> g_sched[UTF_OP_COUNT][UTF_SIZE_CLASSES];
+
+int table_schedule(int op, int c) {
+    const int v = (int)g_sched[op][c].load(std::memory_order_relaxed) - 1;
+    return v >= 0 && v < kNumSchedules ? v : UTF_SCHEDULE_BLOCK;
+}
+
+int forced_schedule() {
+    static const int v = [] {
+        const char *e = std::getenv("UTFGPU_SCHEDULE");
+        if (!e || !*e) return -1;
+        const int x = std::atoi(e);
+        return x >= 0 && x < kNumSchedules ? x : -1;
+    }();
+    return v;
+}
+
+int schedule_for(int op, u64 bytes) {
+    const int f = forced_schedule();
+    return f >= 0 ? f : table_schedule(op, size_class(bytes));
 }
 
 }  // namespace
@@ -330,12 +368,14 @@ inline long long head_bytes(const void *p) { return (long long)(reinterpret_cast
 int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 out_cap, DevResult *res,
                      hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in);
-    const Geometry &g = geometry_for(convert ? UTF_OP_CONVERT_UTF8 : UTF_OP_VALIDATE_UTF8, n);
+    const int op = convert ? UTF_OP_CONVERT_UTF8 : UTF_OP_VALIDATE_UTF8;
+    const Geometry &g = geometry_for(op, n);
     const u64 nt = g.utf8_tiles_for(head, (long long)n);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (g.utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res, s) !=
+    if (g.utf8_tiles(convert, frame_of(in), head, (long long)n, out, out_cap, w->status, w->ctrl, res,
+                     schedule_for(op, n), s) !=
         hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
@@ -345,12 +385,14 @@ int32_t enqueue_utf8(bool convert, const uint8_t *in, u64 n, uint16_t *out, u64 
 int32_t enqueue_utf16(bool convert, const uint16_t *in, u64 m, uint8_t *out, u64 out_cap, DevResult *res,
                       hipStream_t s, Workspace **wso) {
     const long long head = head_bytes(in) / 2;
-    const Geometry &g = geometry_for(convert ? UTF_OP_CONVERT_UTF16LE : UTF_OP_VALIDATE_UTF16LE, 2 * m);
+    const int op = convert ? UTF_OP_CONVERT_UTF16LE : UTF_OP_VALIDATE_UTF16LE;
+    const Geometry &g = geometry_for(op, 2 * m);
     const u64 nt = g.utf16_tiles_for(head, (long long)m);
     Workspace *w;
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (!res) res = w->dres;
-    if (g.utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res, s) !=
+    if (g.utf16_tiles(convert, frame_of(in), head, (long long)m, out, out_cap, w->status, w->ctrl, res,
+                      schedule_for(op, 2 * m), s) !=
         hipSuccess)
         return UTF_ERR_HIP;
     *wso = w;
@@ -597,7 +639,8 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     if (get_batch(w, nt, g.tile_bytes(), g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                          w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr, s) != hipSuccess)
+                          w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr,
+                          schedule_for(UTF_OP_BATCH_UTF8, n), s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
@@ -623,7 +666,8 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (get_batch(w, nt, g.tile_bytes() / 2, g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
                            reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
-                           w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr, s) != hipSuccess)
+                           w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr,
+                           schedule_for(UTF_OP_BATCH_UTF16LE, 2 * m), s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
@@ -644,12 +688,12 @@ int32_t convert_utf8_to_utf16le_noalloc_async(const uint8_t *in, uint64_t n, uin
     u64 *p = nullptr;
     if (noalloc_scratch(s, &p) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf8_tiles(true, frame_of(in), head, (long long)n, out, out_cap, p + kNoAllocCtrlWords,
-                     reinterpret_cast<Ctrl *>(p), r, s) != hipSuccess)
+                     reinterpret_cast<Ctrl *>(p), r, schedule_for(UTF_OP_CONVERT_UTF8, n), s) != hipSuccess)
         return UTF_ERR_HIP;
     return UTF_OK;
 }
 
-const char *utfgpu_version(void) { return "utfgpu 0.1 gfx950"; }
+const char *utfgpu_version(void) { return "utfgpu 0.2 gfx950"; }
 
 uint64_t utfgpu_tile_bytes(void) { return kGeometries[0].tile_bytes(); }
 
@@ -678,5 +722,18 @@ int32_t utfgpu_get_geometry(int32_t op, int32_t size_class) {
 }
 
 int32_t utfgpu_size_class(uint64_t bytes) { return size_class(bytes); }
+
+int32_t utfgpu_set_schedule(int32_t op, int32_t size_class, int32_t schedule) {
+    if (op < 0 || op >= UTF_OP_COUNT || size_class < 0 || size_class >= UTF_SIZE_CLASSES) return UTF_ERR_ARG;
+    if (schedule < -1 || schedule >= kNumSchedules) return UTF_ERR_ARG;
+    g_sched[op][size_class].store((uint8_t)(schedule < 0 ? 0 : schedule + 1), std::memory_order_relaxed);
+    return UTF_OK;
+}
+
+int32_t utfgpu_get_schedule(int32_t op, int32_t size_class) {
+    if (op < 0 || op >= UTF_OP_COUNT || size_class < 0 || size_class >= UTF_SIZE_CLASSES) return UTF_ERR_ARG;
+    const int f = forced_schedule();
+    return f >= 0 ? f : table_schedule(op, size_class);
+}
 
 }  // extern "C"

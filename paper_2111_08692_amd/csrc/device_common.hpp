@@ -226,16 +226,19 @@ __device__ __forceinline__ uint32_t keep_range(uint32_t x, long long p, long lon
 }
 
 // ------------------------------------------------------------------------
-// Tile tickets (batched calls)
+// Tile tickets (the ticket-order scan schedule)
 // ------------------------------------------------------------------------
-// Batched calls take each workgroup's tile index from a counter in the
+// In ticket order a workgroup takes its tile index from a counter in the
 // control block, in the order the workgroups start, instead of using the
 // workgroup index: every tile before a running tile then belongs to a
 // workgroup that has already started, so a look-back never waits on a
-// workgroup the hardware has not placed -- which, with several batched
-// kernels in flight on other streams, can happen for a while.  (Not used for
-// single-buffer calls: the same-address atomic costs them a few percent.)
-// Run by the whole workgroup; `slot` is a __shared__ word.
+// workgroup the hardware has not placed -- which, with several look-back
+// kernels in flight on other streams, can happen for a while.  The finalize
+// kernel resets the counter.  Run by the whole workgroup; `slot` is a
+// __shared__ word.  The tile kernels are compiled for both schedules (a
+// template argument, so block order carries no trace of the counter); the
+// launchers take the schedule index of the C ABI.
+constexpr int kScheduleTicket = 1;
 __device__ __forceinline__ u64 take_ticket(Ctrl *ctrl, uint32_t *slot, uint32_t tid) {
     if (tid == 0) *slot = (uint32_t)__hip_atomic_fetch_add(&ctrl->ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();

@@ -481,7 +481,7 @@ __device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g
 // 16 bits: a tile emits at most three bytes per word.
 static_assert(3 * kTileUnits <= 65536, "16-bit block offsets");
 
-template <bool kConvert, bool kBatch>
+template <bool kConvert, bool kBatch, bool kTicket>
 // Four waves per SIMD: the kernel needs about 93 VGPRs.  Held to six waves
 // per SIMD (80 VGPRs) the compiler spills VGPRs to scratch beside its SGPR
 // spills, and that build gave a wrong first-error result in a sequence of
@@ -490,6 +490,7 @@ template <bool kConvert, bool kBatch>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
     u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
+    static_assert(kConvert || !kTicket, "validation has no scan: tiles in block order");
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords16 : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
     __shared__ u64 s_prefix;
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
     __shared__ uint32_t s_ticket;
-    const u64 tile = kBatch ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
+    const u64 tile = kTicket ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
     const long long end = head + m;
     const long long wbase = (long long)tile * kTileUnits + (long long)wave * kWaveUnits;
 
@@ -657,14 +658,18 @@ u64 utf16_tiles_for(long long head, long long m) { return (u64)((head + m + kTil
 int partial_blocks(long long units, long long units_per_block);
 
 hipError_t launch_utf16_tiles(bool convert, const uint8_t *frame, long long head, long long m, uint8_t *out,
-                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
+                              u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, int schedule,
+                              hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
     const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (convert)
-        hipLaunchKernelGGL((utf16_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    if (convert && schedule == kScheduleTicket)
+        hipLaunchKernelGGL((utf16_tile_kernel<true, false, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
-    else
-        hipLaunchKernelGGL((utf16_tile_kernel<false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    else if (convert)
+        hipLaunchKernelGGL((utf16_tile_kernel<true, false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
+    else   // no scan: the schedule does not apply
+        hipLaunchKernelGGL((utf16_tile_kernel<false, false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -729,13 +734,17 @@ hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long
 hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
                               uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                               Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream) {
+                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,
+                              hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
     hipError_t e = launch_batch_prep(offsets, k, head, m, starts, bad, kWaveUnits, wavestr, ntiles * kWaves, stream);
     if (e != hipSuccess) return e;
     const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr, wavestr};
-    if (m > 0)
-        hipLaunchKernelGGL((utf16_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    if (m > 0 && schedule == kScheduleTicket)
+        hipLaunchKernelGGL((utf16_tile_kernel<true, true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
+    else if (m > 0)
+        hipLaunchKernelGGL((utf16_tile_kernel<true, true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(batch_post16_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, m, bc, ctrl, out_offsets,

@@ -1029,10 +1029,11 @@ __device__ __forceinline__ bool check_values(const LaneBytes &t, uint32_t lane) 
 // 16 bits: a tile emits at most one word per byte.
 static_assert(kTileBytes <= 65536, "16-bit block offsets");
 
-template <bool kConvert, bool kBatch>
+template <bool kConvert, bool kBatch, bool kTicket>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf8_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long n, uint16_t *__restrict__ out, u64 out_cap,
     u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
+    static_assert(kConvert || !kTicket, "validation has no scan: tiles in block order");
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
     __shared__ u64 s_prefix;
@@ -1042,7 +1043,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches on it
     const long long end = head + n;
     __shared__ uint32_t s_ticket;
-    const u64 tile = kBatch ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
+    const u64 tile = kTicket ? take_ticket(ctrl, &s_ticket, tid) : (u64)blockIdx.x;
     const long long wbase = (long long)tile * kTileBytes + (long long)wave * kWaveBytes;
     LaneBytes t;
     issue_span(frame, end, wbase, lane, t);
@@ -1328,14 +1329,18 @@ u64 utf8_tiles_for(long long head, long long n) {
 }
 
 hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head, long long n, uint16_t *out,
-                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, hipStream_t stream) {
+                             u64 out_cap, u64 *status, Ctrl *ctrl, DevResult *result, int schedule,
+                             hipStream_t stream) {
     const u64 ntiles = utf8_tiles_for(head, n);
     const BatchCtx none = {nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (convert)
-        hipLaunchKernelGGL((utf8_tile_kernel<true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    if (convert && schedule == kScheduleTicket)
+        hipLaunchKernelGGL((utf8_tile_kernel<true, false, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
-    else
-        hipLaunchKernelGGL((utf8_tile_kernel<false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    else if (convert)
+        hipLaunchKernelGGL((utf8_tile_kernel<true, false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
+    else   // no scan: the schedule does not apply
+        hipLaunchKernelGGL((utf8_tile_kernel<false, false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1446,14 +1451,18 @@ hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long
 hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
-                             u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, hipStream_t stream) {
+                             u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,
+                             hipStream_t stream) {
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
     const u64 ntiles = utf8_tiles_for(head, n);
     hipError_t e = launch_batch_prep(offsets, k, head, n, starts, bad, kWaveBytes, wavestr, ntiles * kWaves, stream);
     if (e != hipSuccess) return e;
     const BatchCtx bc = {offsets, k, (const uint16_t *)starts, blockoff, tilepre, serr, wavestr};
-    if (n > 0)
-        hipLaunchKernelGGL((utf8_tile_kernel<true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+    if (n > 0 && schedule == kScheduleTicket)
+        hipLaunchKernelGGL((utf8_tile_kernel<true, true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
+                           head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
+    else if (n > 0)
+        hipLaunchKernelGGL((utf8_tile_kernel<true, true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
     hipLaunchKernelGGL(batch_post_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, n, bc, ctrl, out_offsets,
                        results, out_cap, (const uint32_t *)bad, starts);

@@ -1,13 +1,15 @@
-"""GPU parity of every compiled tile geometry, and of the tuner's table.
+"""GPU parity of every compiled tile geometry in both scan schedules, and
+of the tuner's tables.
 
-Each geometry is forced for every operation and size class, and
-the single-buffer and batched calls are checked against the CPU oracle, bit
-for bit, at sizes and positions placed on that geometry's own row, wave and
-tile boundaries (ragged tails, straddling characters and errors, random
-bytes, stage overflow).  The rest of the suite runs the shipped table
-(8 KiB tiles up to 4 MiB, the 8 x 4 build above, for most calls).
-Then a short tuning run must produce a table that names compiled geometries,
-installs it, survives a JSON round trip, and leaves every result unchanged.
+Each (geometry, schedule) pair is forced for every operation and size
+class, and the single-buffer and batched calls are checked against the CPU
+oracle, bit for bit, at sizes and positions placed on that geometry's own
+row, wave and tile boundaries (ragged tails, straddling characters and
+errors, random bytes, stage overflow).  The rest of the suite runs the
+shipped tables (8 KiB tiles up to 4 MiB, the 8 x 4 build above, for most
+calls; block order everywhere).  Then a short tuning run must produce tables
+that name compiled geometries and known schedules, install them, survive a
+JSON round trip, and leave every result unchanged.
 """
 import numpy as np
 import pytest
@@ -36,19 +38,24 @@ def G():
     return G
 
 
-def _force(G, g):
+def _force(G, g, s=-1):
     for op in range(G.OP_COUNT):
         for c in range(G.SIZE_CLASSES):
             assert G.set_geometry(op, c, g) == G.OK
+            assert G.set_schedule(op, c, s) == G.OK
 
 
-@pytest.fixture(params=range(0, _NGEOM), ids=lambda g: f"geometry{g}")
+_PAIRS = [(g, s) for s in (0, 1) for g in range(_NGEOM)]
+
+
+@pytest.fixture(params=_PAIRS, ids=lambda p: f"geometry{p[0]}-{('block', 'ticket')[p[1]]}")
 def geom(G, request):
-    g = request.param
+    g, s = request.param
     waves, rows, tile = G.geometries()[g]
-    _force(G, g)
-    assert all(G.get_geometry(op, c) == g for op in range(G.OP_COUNT) for c in (0, 17, 40))
-    yield {"index": g, "waves": waves, "rows": rows, "tile": tile, "wave": rows * 1024}
+    _force(G, g, s)
+    assert all(G.get_geometry(op, c) == g and G.get_schedule(op, c) == s
+               for op in range(G.OP_COUNT) for c in (0, 17, 40))
+    yield {"index": g, "schedule": s, "waves": waves, "rows": rows, "tile": tile, "wave": rows * 1024}
     _force(G, -1)
 
 
@@ -136,21 +143,25 @@ def test_tuner_table_and_parity(G, orc, tmp_path):
     sample = make_buffer("mix1m", 1 << 20, seed=5).data
     sizes = (1 << 15, 1 << 18, 1 << 21)
     T.reset()
-    shipped = [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)]
+    shipped = [[(G.get_geometry(op, c), G.get_schedule(op, c)) for c in range(G.SIZE_CLASSES)]
+               for op in range(G.OP_COUNT)]
     try:
         res = T.tune(sample, sizes=sizes, min_ms=0.3, reps=2)
         names = T.geometry_names()
-        assert res["geometries"] == names
-        assert set(res["table"]) == set(T.OPS)
+        assert res["geometries"] == names and res["schedules"] == list(G.SCHEDULE_NAMES)
+        assert len(res["candidates"]) == 2 * len(names)
+        assert set(res["table"]) == set(T.OPS) and set(res["schedule"]) == set(T.OPS)
         for op, rows in res["measured"].items():
             assert len(rows) == len(sizes)
             for r in rows:
-                assert len(r["us"]) == len(names) and min(r["us"]) > 0 and r["choice"] in names
-        # installed: the library reports the table's choices
+                assert len(r["us"]) == len(res["candidates"]) and min(r["us"]) > 0
+                assert r["choice"] in res["candidates"]
+        # installed: the library reports the tables' choices
         for op, row in res["table"].items():
             assert len(row) == G.SIZE_CLASSES
             for c in (0, 15, 18, 21, 40):
                 assert G.get_geometry(T.OPS[op], c) == names.index(row[c])
+                assert G.get_schedule(T.OPS[op], c) == G.SCHEDULE_NAMES.index(res["schedule"][op][c])
         # results under the tuned table equal the oracle's
         for n in (30_000, 250_000, 2_000_000):
             b = make_buffer("mix1m", n, seed=n, error_rate=1e-5, error_seed=n + 1)
@@ -163,11 +174,14 @@ def test_tuner_table_and_parity(G, orc, tmp_path):
         path = tmp_path / "tune.json"
         T.save(res, str(path))
         T.reset()
-        assert [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)] == shipped
+        assert [[(G.get_geometry(op, c), G.get_schedule(op, c)) for c in range(G.SIZE_CLASSES)]
+                for op in range(G.OP_COUNT)] == shipped
         again = T.apply_file(str(path))
-        assert again["table"] == res["table"]
+        assert again["table"] == res["table"] and again["schedule"] == res["schedule"]
         for op, row in res["table"].items():
             assert [names[G.get_geometry(T.OPS[op], c)] for c in range(G.SIZE_CLASSES)] == row
+            assert [G.SCHEDULE_NAMES[G.get_schedule(T.OPS[op], c)] for c in range(G.SIZE_CLASSES)] \
+                == res["schedule"][op]
     finally:
         T.reset()
 

@@ -1,8 +1,9 @@
 """The look-back's helping path: with UTFGPU_LOOKBACK_SPINS=0 a wave that
 finds a predecessor's status word missing computes that tile's aggregate
 itself at once.  Run in a child process (the knob is read once per
-process); every result must still match the oracle, single buffers and
-batched strings alike."""
+process), in block order and in ticket order (UTFGPU_SCHEDULE); every
+result must still match the oracle, single buffers and batched strings
+alike."""
 import os
 import subprocess
 import sys
@@ -14,7 +15,7 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 CHILD = r'''
-import sys
+import os, sys
 sys.path.insert(0, ROOT_DIR)
 import numpy as np, torch
 import oracle as O
@@ -57,12 +58,14 @@ for enc in ("utf-8", "utf-16-le"):
     assert np.array_equal(st, ost) and np.array_equal(cnt, ocnt), enc
     valid = np.repeat(ost == O.OK, np.diff(ooff))
     assert np.array_equal(got[:ooff[-1]][valid], oout[valid]), enc
+assert G.get_schedule(G.OP_CONVERT_UTF8, 22) == int(os.environ["UTFGPU_SCHEDULE"])
 print("helping path ok", flush=True)
 '''
 
 
-def test_helping_path_matches_oracle():
-    env = dict(os.environ, UTFGPU_LOOKBACK_SPINS="0")
+@pytest.mark.parametrize("schedule", ["0", "1"], ids=["block", "ticket"])
+def test_helping_path_matches_oracle(schedule):
+    env = dict(os.environ, UTFGPU_LOOKBACK_SPINS="0", UTFGPU_SCHEDULE=schedule)
     r = subprocess.run([sys.executable, "-c", "ROOT_DIR = " + repr(ROOT) + "\n" + CHILD], env=env, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]

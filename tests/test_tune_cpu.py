@@ -1,7 +1,8 @@
-"""CPU checks of the geometry tuning table and the tuner's host logic: the
-table calls of the C ABI (host state, no GPU), size classes, argument
-checks, the table fill and choice rules, the character-boundary cuts of the
-tuner's inputs, and installing / refusing a saved table."""
+"""CPU checks of the geometry and scan-schedule tuning tables and the
+tuner's host logic: the table calls of the C ABI (host state, no GPU), size
+classes, argument checks, the table fill and choice rules, the candidate
+list, the character-boundary cuts of the tuner's inputs, and installing /
+refusing a saved table."""
 import json
 import os
 
@@ -20,6 +21,7 @@ def G():
     for op in range(G.OP_COUNT):
         for c in range(G.SIZE_CLASSES):
             G.set_geometry(op, c, -1)
+            G.set_schedule(op, c, -1)
 
 
 @pytest.fixture(scope="module")
@@ -80,6 +82,35 @@ def test_set_get_and_argument_checks(G):
     assert G.load().utfgpu_geometry(ng, None, None, None) == G.ERR_ARG
 
 
+def test_schedules_shipped_set_get_and_argument_checks(G):
+    assert (G.SCHEDULE_BLOCK, G.SCHEDULE_TICKET) == (0, 1) and G.SCHEDULE_NAMES == ("block", "ticket")
+    for op in range(G.OP_COUNT):
+        for c in range(G.SIZE_CLASSES):
+            assert G.set_schedule(op, c, -1) == G.OK
+    # shipped: block order for every operation and class
+    assert all(G.get_schedule(op, c) == G.SCHEDULE_BLOCK for op in range(G.OP_COUNT) for c in range(G.SIZE_CLASSES))
+    g = G.get_geometry(G.OP_BATCH_UTF16LE, 27)
+    assert G.set_schedule(G.OP_BATCH_UTF16LE, 27, G.SCHEDULE_TICKET) == G.OK
+    assert G.get_schedule(G.OP_BATCH_UTF16LE, 27) == G.SCHEDULE_TICKET
+    # the geometry and the other entries are untouched
+    assert G.get_geometry(G.OP_BATCH_UTF16LE, 27) == g
+    assert G.get_schedule(G.OP_BATCH_UTF16LE, 26) == 0 and G.get_schedule(G.OP_BATCH_UTF8, 27) == 0
+    assert G.set_schedule(G.OP_BATCH_UTF16LE, 27, -1) == G.OK and G.get_schedule(G.OP_BATCH_UTF16LE, 27) == 0
+    for op, c, v in ((-1, 0, 0), (G.OP_COUNT, 0, 0), (0, -1, 0), (0, G.SIZE_CLASSES, 0), (0, 0, 2), (0, 0, -2)):
+        assert G.set_schedule(op, c, v) == G.ERR_ARG, (op, c, v)
+    assert G.get_schedule(G.OP_COUNT, 0) == G.ERR_ARG and G.get_schedule(0, G.SIZE_CLASSES) == G.ERR_ARG
+
+
+def test_candidates(T, G):
+    ng = len(G.geometries())
+    c = T.candidates()
+    assert c[0] == (0, 0) and len(c) == 2 * ng and len(set(c)) == len(c)
+    assert set(c) == {(g, s) for g in range(ng) for s in (0, 1)}
+    assert T.candidates(False) == [(g, 0) for g in range(ng)]
+    names = T.geometry_names()
+    assert T.candidate_name(0, 1, names) == names[0] + "/ticket"
+
+
 def test_choose_and_fill(T):
     assert T.choose([10.0, 9.0, 11.0], 0.03) == 1
     assert T.choose([10.0, 9.8, 11.0], 0.03) == 0   # within the margin: the current geometry stays
@@ -114,14 +145,22 @@ def test_input_cuts_keep_characters_whole(T):
 
 def _table(T, G, pick):
     names = T.geometry_names()
-    return {"library": G.version(), "geometries": names, "min_gain": 0.03, "string_bytes": 4096, "measured": {},
+    return {"library": G.version(), "geometries": names, "schedules": list(G.SCHEDULE_NAMES), "min_gain": 0.03,
+            "string_bytes": 4096, "measured": {},
             "table": {op: [names[pick(i, c) % len(names)] for c in range(G.SIZE_CLASSES)]
-                      for i, op in enumerate(T.OPS)}}
+                      for i, op in enumerate(T.OPS)},
+            "schedule": {op: [G.SCHEDULE_NAMES[(i * c) % 2] for c in range(G.SIZE_CLASSES)]
+                         for i, op in enumerate(T.OPS)}}
+
+
+def _state(G):
+    return [[(G.get_geometry(op, c), G.get_schedule(op, c)) for c in range(G.SIZE_CLASSES)]
+            for op in range(G.OP_COUNT)]
 
 
 def test_apply_save_load_reset(T, G, tmp_path):
     T.reset()
-    shipped = [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)]
+    shipped = _state(G)
     res = _table(T, G, lambda i, c: i + c)
     path = tmp_path / "t.json"
     T.save(res, str(path))
@@ -130,17 +169,24 @@ def test_apply_save_load_reset(T, G, tmp_path):
     for i, op in enumerate(T.OPS):
         for c in range(G.SIZE_CLASSES):
             assert G.get_geometry(T.OPS[op], c) == (i + c) % n
+            assert G.get_schedule(T.OPS[op], c) == (i * c) % 2
     T.reset()
-    assert [[G.get_geometry(op, c) for c in range(G.SIZE_CLASSES)] for op in range(G.OP_COUNT)] == shipped
+    assert _state(G) == shipped
 
 
 def test_apply_refuses_a_foreign_table(T, G, tmp_path):
     good = _table(T, G, lambda i, c: 1)
+    T.reset()
+    shipped = _state(G)
+    sched_bad = dict(good["schedule"], validate_utf8=["fifo"] * G.SIZE_CLASSES)
     for bad in (dict(good, geometries=good["geometries"][:-1]), dict(good, library="other 9.9"),
+                dict(good, schedules=["block"]), dict(good, schedule=sched_bad),
+                dict(good, schedule={op: v for op, v in good["schedule"].items() if op != "validate_utf8"}),
                 dict(good, table={"no_such_op": good["table"]["validate_utf8"]}),
                 dict(good, table={"validate_utf8": good["table"]["validate_utf8"][:10]})):
         path = tmp_path / "bad.json"
         path.write_text(json.dumps(bad))
         with pytest.raises(ValueError):
             T.apply_file(str(path))
+        assert _state(G) == shipped   # nothing installed from a refused table
     T.reset()
