@@ -87,6 +87,15 @@ __device__ __forceinline__ void load_span16(const uint8_t *frame, long long head
     }
 }
 
+// An empty asm per data register: later code cannot reuse comparisons made
+// on the words before this point, so their lane masks do not stay live.
+__device__ __forceinline__ void fence_units(LaneUnits &t) {
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(t.d[r][k]));
+}
+
 // The word before / after the lane's chunk of row r.
 __device__ __forceinline__ uint32_t prev_word(const LaneUnits &t, int r, uint32_t lane) {
     const uint32_t p = __shfl_up(t.d[r][3], 1);
@@ -482,18 +491,21 @@ __device__ __forceinline__ void narrow_store_wave(const LaneUnits &t, uint8_t *g
 static_assert(3 * kTileUnits <= 65536, "16-bit block offsets");
 
 template <bool kConvert, bool kBatch, bool kTicket>
-// Four waves per SIMD: the kernel needs about 93 VGPRs.  Held to six waves
-// per SIMD (80 VGPRs) the compiler spills VGPRs to scratch beside its SGPR
-// spills, and that build gave a wrong first-error result in a sequence of
-// calls that this build converts correctly, so the spilling build is not
-// used.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void utf16_tile_kernel(
+// Six waves per SIMD (at most 80 VGPRs, so three 8-wave workgroups share a
+// CU): the kernel waits on loads, barriers and the look-back more than it
+// computes, and the third workgroup fills those waits.  It fits without
+// spilling VGPRs to scratch because (a) the words pass through an empty asm
+// after the survey and after the surrogate check, so the encoders cannot
+// reuse those comparisons and keep their lane masks live, and (b) wave 0
+// parks its words in LDS while it resolves the tile prefix.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void utf16_tile_kernel(
     const uint8_t *__restrict__ frame, long long head, long long m, uint8_t *__restrict__ out, u64 out_cap,
     u64 *__restrict__ status, Ctrl *__restrict__ ctrl, u64 ntiles, int spin_limit, BatchCtx bc) {
     static_assert(kConvert || !kTicket, "validation has no scan: tiles in block order");
     __shared__ __attribute__((aligned(16))) uint32_t stage[kConvert ? kWaves * kStageWords16 : 4];
     __shared__ uint32_t s_wave_tot[kWaves];
     __shared__ u64 s_prefix;
+    __shared__ __attribute__((aligned(16))) uint32_t s_park[kConvert ? kRows * 4 * kWave : 4];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -509,6 +521,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     uint32_t width[kRows];
     uint32_t cls = survey16<kConvert>(t, wbase, head, end, lane, width);
     if (cls == kAscii16 && t.edge) cls = kUpTo2B;   // whole-chunk narrowing: not at the ends
+    fence_units(t);
 
     // a wave holding an unpaired surrogate; when an error before it is
     // already known, its output (past the valid prefix) is not written and
@@ -553,9 +566,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             tile_total += v;
         }
         if (wave == 0) {
+            // wave 0's words wait in LDS while it resolves the tile prefix:
+            // the look-back's registers then fit beside the rest
+            u32x4 *pk = (u32x4 *)s_park;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r)
+                pk[r * kWave + lane] = u32x4{t.d[r][0], t.d[r][1], t.d[r][2], t.d[r][3]};
+            asm volatile("" ::: "memory");
             const u64 prefix = resolve_prefix(status, tile, epoch, spin_limit, tile_total, [=](long long tl) {
                 return tile_width8(frame, head, end, tl);
             });
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                const u32x4 v = pk[r * kWave + lane];
+                t.d[r][0] = v.x; t.d[r][1] = v.y; t.d[r][2] = v.z; t.d[r][3] = v.w;
+            }
             if (lane == 0) {
                 s_prefix = prefix;
                 if (tile == ntiles - 1) st_agent(&ctrl->total, prefix + tile_total);
@@ -569,6 +595,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     (uint16_t)(wave_off + rowbase[r] + off[r]);
         }
         unpaired = find_unpaired();
+        fence_units(t);
         __syncthreads();   // the tile prefix is known
         // an error before the wave is already known: its output lies past
         // the valid prefix and is not written (the error word is read only
