@@ -423,8 +423,26 @@ def host_leg(bufs, aux):
     """Host-resident input and output: one 1 GiB buffer per direction (CJK
     mix) through the chunked, pipelined host path (64 MiB chunks, 3
     streams).  Bounded by PCIe and host copies, reported apart from the HBM
-    roofline."""
+    roofline, beside plain pinned copies over the same link."""
+    import torch
     from paper_2111_08692_amd.host_pipeline import HostPipeline
+    # the link alone: 1 GiB pinned host -> device and device -> pinned host
+    n = 1 << 30
+    hbuf = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    dbuf = torch.empty(n, dtype=torch.uint8, device="cuda")
+    rate = {}
+    for name, dst, src in (("h2d", dbuf, hbuf), ("d2h", hbuf, dbuf)):
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            dst.copy_(src, non_blocking=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        rate[name] = n / best / 1e9
+        aux[f"host_pcie_{name}_GBps"] = round(rate[name], 2)
+    del hbuf, dbuf
     p = HostPipeline(chunk_bytes=64 << 20, nstreams=3)
     for mix, enc, kind, b in bufs:
         if mix != "cjk" or kind != "valid":
@@ -436,6 +454,9 @@ def host_leg(bufs, aux):
         d = "8to16" if enc == "utf-8" else "16to8"
         aux[f"host_pipeline_cjk_{d}_GBps"] = round(b.data.nbytes / p.last["seconds"] / 1e9, 2)
         aux[f"host_pipeline_cjk_{d}_pcie_bytes"] = int(b.data.nbytes + out.nbytes)
+        # the least time the link allows: input up and output down, overlapped
+        link_s = max(b.data.nbytes / (rate["h2d"] * 1e9), out.nbytes / (rate["d2h"] * 1e9))
+        aux[f"host_pipeline_cjk_{d}_frac_of_link"] = round(link_s / p.last["seconds"], 3)
 
 
 def main():
@@ -559,7 +580,8 @@ def main():
         kern_bytes[name] += alg * args.steps
         key = f"{mix}/{'8to16' if enc == 'utf-8' else '16to8'}/{kind}"
         per[key] = {"input_GBps": round(nin / t / 1e9, 1), "hbm_GBps": round(alg / t / 1e9, 1),
-                    "roofline_frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 3), "ms": round(t * 1e3, 4)}
+                    "roofline_frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 3), "ms": round(t * 1e3, 4),
+                    "input_bytes": nin, "output_units": int(out_units[i])}
     dom = max(kern_time, key=kern_time.get)
     achieved = kern_bytes[dom] / kern_time[dom] / 1e9
     launches = args.steps * sum(1 for _, enc, _, _ in bufs if (enc == "utf-8") == dom.startswith("utf8"))
