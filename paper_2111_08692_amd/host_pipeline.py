@@ -14,9 +14,14 @@ the first failing chunk still reports the input's first error.)
 
 Per chunk and stream: the host copies the chunk into a pinned staging
 buffer, then the stream copies it to the device, converts it and copies
-the result back; when the host collects the chunk it copies exactly the
-chunk's output back, while the other streams carry on.  The throughput of this path is
-bounded by PCIe and host copies, not by HBM.
+the result back.  When the stream is needed again the host reads that
+result and queues the copy of exactly the chunk's output to a pinned
+buffer; the host moves it into the caller's output array one round later,
+so device-to-host copies overlap the staging of the next chunks.  Chunks
+are collected in order, so each output lands at the running sum of the
+counts before it.  Host copies are torch CPU copies (several threads).
+The throughput of this path is bounded by PCIe and host copies, not by
+HBM.
 """
 from __future__ import annotations
 
@@ -83,31 +88,53 @@ class HostPipeline:
         self.last = {}
 
     def _run(self, data: np.ndarray, to16: bool) -> Tuple[int, int, np.ndarray]:
-        unit = 1 if to16 else 2
+        unit = 1 if to16 else 2          # input bytes per unit
+        out_unit = 2 if to16 else 1      # output bytes per unit
         raw = np.ascontiguousarray(data).view(np.uint8)
+        raw_t = torch.from_numpy(raw)
         cuts = cuts_utf8(data, self.chunk) if to16 else cuts_utf16(data, self.chunk // 2)
         ns = len(self.streams)
-        pieces: List[np.ndarray] = []
+        # at most 2 output bytes per UTF-8 byte, 3 per UTF-16 unit
+        final = np.empty(2 * raw.size if to16 else 3 * (raw.size // 2), dtype=np.uint8)
+        final_t = torch.from_numpy(final)
+        written = 0
         first_err = None
-        pend = [None] * ns   # (chunk index, start unit) per stream
+        pend = [None] * ns       # (chunk index, start unit) per stream: converted, result not read
+        out_pend = [None] * ns   # (event, output offset, bytes) per stream: copy to h_out queued
         t0 = time.perf_counter()
         nchunks = len(cuts) - 1
 
+        def finish_out(si):
+            # the stream's last output copy is done: move it into place
+            if out_pend[si] is None:
+                return
+            ev, off, nb = out_pend[si]
+            ev.synchronize()
+            final_t[off:off + nb].copy_(self.h_out[si][:nb])
+            out_pend[si] = None
+
         def collect(si):
-            # the chunk's result, then exactly its output (the other streams keep going)
-            nonlocal first_err
+            # the chunk's result, then queue the copy of exactly its output
+            nonlocal first_err, written
             ci, start = pend[si]
+            pend[si] = None
             self.events[si].synchronize()
             st, cnt = decode_result(self.h_res[si])
             if st != OK:
                 if first_err is None or ci < first_err[0]:
                     first_err = (ci, st, start + cnt)
-            else:
-                nb = cnt * (2 if to16 else 1)
-                with torch.cuda.stream(self.streams[si]):
-                    self.h_out[si][:nb].copy_(self.d_out[si][:nb])
-                pieces.append((ci, self.h_out[si][:nb].numpy().copy()))
-            pend[si] = None
+                return
+            if first_err is not None:
+                return
+            finish_out(si)   # h_out[si] is free again
+            nb = cnt * out_unit
+            s = self.streams[si]
+            with torch.cuda.stream(s):
+                self.h_out[si][:nb].copy_(self.d_out[si][:nb], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(s)
+            out_pend[si] = (ev, written, nb)
+            written += nb
 
         for ci in range(nchunks):
             if first_err is not None and first_err[0] < ci:
@@ -120,7 +147,7 @@ class HostPipeline:
             a, b = cuts[ci], cuts[ci + 1]
             nb = (b - a) * unit
             hb = self.h_in[si]
-            hb[:nb].numpy()[:] = raw[a * unit:b * unit]
+            hb[:nb].copy_(raw_t[a * unit:b * unit])
             s = self.streams[si]
             with torch.cuda.stream(s):
                 self.d_in[si][:nb].copy_(hb[:nb], non_blocking=True)
@@ -139,14 +166,20 @@ class HostPipeline:
                 ev.record(s)
             self.events[si] = ev
             pend[si] = (ci, a)
-        for si in range(ns):
+        # the remaining chunks in order (ci, ci + 1, ... wrap around the streams)
+        for k in range(ns):
+            si = (nchunks + k) % ns
             if pend[si] is not None:
                 collect(si)
+        for k in range(ns):
+            si = (nchunks + k) % ns
+            if out_pend[si] is not None:
+                finish_out(si)
+        torch.cuda.synchronize(self.dev)
         self.last = {"seconds": time.perf_counter() - t0, "chunks": nchunks, "input_bytes": raw.size}
         if first_err is not None:
             return first_err[1], first_err[2], np.zeros(0, dtype=np.uint16 if to16 else np.uint8)
-        pieces.sort(key=lambda p: p[0])
-        out = np.concatenate([p for _, p in pieces]) if pieces else np.zeros(0, dtype=np.uint8)
+        out = final[:written]
         out = out.view(np.uint16) if to16 else out
         return OK, int(out.size), out
 
