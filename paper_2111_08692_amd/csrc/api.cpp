@@ -37,12 +37,12 @@
     hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);                                                 \
     hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets,       \
                                  u64 k, uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
-                                 u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,            \
+                                 u64 *status, Ctrl *ctrl, uint32_t *starts,            \
                                  uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr,   \
                                  int schedule, hipStream_t stream);                                               \
     hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets,      \
                                   u64 k, uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
-                                  u64 *status, Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts,           \
+                                  u64 *status, Ctrl *ctrl, uint32_t *starts,           \
                                   uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad,                     \
                                   uint32_t *wavestr, int schedule, hipStream_t stream);                           \
     }                                                                                                             \
@@ -638,7 +638,7 @@ int32_t convert_utf8_to_utf16le_batch_async(const uint8_t *in, uint64_t n, const
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (get_batch(w, nt, g.tile_bytes(), g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf8_batch(n > 0 ? frame_of(in) : nullptr, head, (long long)n, offsets, k, out, out_cap, out_offsets,
-                          reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
+                          reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->starts,
                           w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr,
                           schedule_for(UTF_OP_BATCH_UTF8, n), s) != hipSuccess)
         return UTF_ERR_HIP;
@@ -665,7 +665,7 @@ int32_t convert_utf16le_to_utf8_batch_async(const uint16_t *in, uint64_t m, cons
     if (get_ws(s, nt, &w) != hipSuccess) return UTF_ERR_HIP;
     if (get_batch(w, nt, g.tile_bytes() / 2, g.waves, k, s) != hipSuccess) return UTF_ERR_HIP;
     if (g.utf16_batch(m > 0 ? frame_of(in) : nullptr, head, (long long)m, offsets, k, out, out_cap, out_offsets,
-                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->dres, w->starts,
+                           reinterpret_cast<DevResult *>(results), w->status, w->ctrl, w->starts,
                            w->blockoff, w->tilepre, w->serr, &w->ctrl->bad, w->wavestr,
                            schedule_for(UTF_OP_BATCH_UTF16LE, 2 * m), s) != hipSuccess)
         return UTF_ERR_HIP;

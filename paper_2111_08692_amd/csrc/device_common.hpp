@@ -90,16 +90,18 @@ struct DevResult {
 };
 
 // Per-workspace control block, the fields the tiles write each on its own
-// 64-byte line.  The finalize kernel of every call resets `err` and
-// `total` and advances `epoch`, so each call finds it in the same state.
+// 64-byte line.  The last kernel of every call (the finalize kernel, or for
+// batched calls the last workgroup of the post kernel) resets the per-call
+// fields and advances `epoch`, so each call finds it in the same state.
 // Epochs run 1 .. period-1; the call whose finalize would reach `period`
 // clears every status word of the workspace and starts again at 1, so a
 // status word left by an earlier call never carries the current epoch,
 // however many calls (eager or replayed from a captured graph) ran.
 struct Ctrl {
     u64 err;        // min over (position << 4 | kind); ~0 when no error
-    u64 ticket;     // batched calls: the next tile index to hand out
-    u64 pad0[6];
+    u64 ticket;     // ticket order: the next tile index to hand out
+    u64 done;       // batched calls: post-kernel workgroups finished
+    u64 pad0[5];
     u64 total;      // output units of the whole call (written by the last tile)
     uint32_t bad;   // batched calls: the offsets are not a partition of the input
     uint32_t pad_b;
@@ -350,6 +352,42 @@ __device__ __forceinline__ u64 resolve_prefix(u64 *status, u64 t, u64 epoch, int
     const u64 prefix = lookback(status, (long long)t, epoch, spin_limit, agg);
     if (lane == 0) st_agent(status + t * kStatusStride, pack_status(kFlagPrefix, epoch, prefix + tile_total));
     return prefix;
+}
+
+// End of a call: reset the per-call fields of the control block and
+// advance the epoch.  The call that would reach the period first clears
+// every status word of the workspace (with all `nthreads` threads of the
+// calling workgroup) and starts again at epoch 1.  Run by a whole
+// workgroup, after every other reader of the per-call fields is done.
+__device__ __forceinline__ void reset_control(Ctrl *ctrl, uint32_t tid, uint32_t nthreads) {
+    const u64 next = ld_agent(&ctrl->epoch) + 1;
+    const bool wrap = next >= ctrl->period;
+    __syncthreads();   // every thread has read the epoch before thread 0 advances it
+    if (wrap) {
+        u64 *st = ctrl->status;
+        const u64 cap = ctrl->status_cap;
+        for (u64 t = tid; t < cap; t += nthreads) st_agent(st + t * kStatusStride, 0);
+    }
+    if (tid != 0) return;
+    st_agent(&ctrl->err, ~0ull);
+    st_agent(&ctrl->total, 0);
+    st_agent(&ctrl->ticket, 0);
+    st_agent(&ctrl->done, 0);
+    ctrl->bad = 0;
+    st_agent(&ctrl->epoch, wrap ? 1 : next);
+}
+
+// Batched calls end in their post kernel: every workgroup counts itself
+// done once its threads have read what they need of the control block, and
+// the last one resets it (so no separate finalize launch is needed).
+__device__ __forceinline__ void batch_call_done(Ctrl *ctrl, uint32_t tid) {
+    __shared__ uint32_t s_last;
+    __syncthreads();   // every thread of the workgroup has finished its string
+    if (tid == 0)
+        s_last = __hip_atomic_fetch_add(&ctrl->done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 (u64)gridDim.x - 1;
+    __syncthreads();
+    if (s_last) reset_control(ctrl, tid, blockDim.x);
 }
 
 // ------------------------------------------------------------------------

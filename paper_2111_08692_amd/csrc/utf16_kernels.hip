@@ -721,11 +721,9 @@ __device__ u64 batch_out_offset16(const uint8_t *frame, long long head, long lon
 
 // Per string: output offsets, result, and the reset of its error word and
 // start bit for the next call.
-__global__ void batch_post16_kernel(const uint8_t *frame, long long head, long long m, BatchCtx bc, Ctrl *ctrl,
-                                    int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
-                                    uint32_t *starts) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > bc.k) return;
+__device__ __forceinline__ void post_string16(const uint8_t *frame, long long head, long long m, const BatchCtx &bc,
+                                              Ctrl *ctrl, int64_t *out_offsets, DevResult *results, u64 out_cap,
+                                              const uint32_t *bad, uint32_t *starts, u64 i) {
     const bool ok = *bad == 0;
     const u64 total = ld_agent(&ctrl->total);
     const int64_t a = bc.offsets[i];
@@ -755,12 +753,22 @@ __global__ void batch_post16_kernel(const uint8_t *frame, long long head, long l
     }
 }
 
+// Thread i <= k: string i's output offset and result; then the last
+// workgroup to finish resets the control block for the next call.
+__global__ void batch_post16_kernel(const uint8_t *frame, long long head, long long m, BatchCtx bc, Ctrl *ctrl,
+                                    int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
+                                    uint32_t *starts) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= bc.k) post_string16(frame, head, m, bc, ctrl, out_offsets, results, out_cap, bad, starts, i);
+    batch_call_done(ctrl, threadIdx.x);
+}
+
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
                              uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream);
 
 hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets, u64 k,
                               uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
-                              Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                              Ctrl *ctrl, uint32_t *starts, uint16_t *blockoff,
                               u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,
                               hipStream_t stream) {
     const u64 ntiles = utf16_tiles_for(head, m);
@@ -776,8 +784,7 @@ hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m,
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(batch_post16_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, m, bc, ctrl, out_offsets,
                        results, out_cap, (const uint32_t *)bad, starts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_finalize(ctrl, scratch_result, nullptr, kFinConvert, (u64)m, out_cap, nullptr, 0, stream);
+    return hipGetLastError();
 }
 
 hipError_t launch_utf8_length(const uint8_t *frame, long long head, long long m, u64 *partials, Ctrl *ctrl,

@@ -1257,34 +1257,22 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(Ctrl *ctrl, DevResult 
         }
         return;
     }
-    // the call that would reach the period clears the status words
-    const u64 next = ld_agent(&ctrl->epoch) + 1;
-    const bool wrap = next >= ctrl->period;
-    __syncthreads();   // every thread has read the epoch before thread 0 advances it
-    if (wrap) {
-        u64 *st = ctrl->status;
-        const u64 cap = ctrl->status_cap;
-        for (u64 t = tid; t < cap; t += kBlock) st_agent(st + t * kStatusStride, 0);
+    if (tid == 0) {
+        const u64 e = ld_agent(&ctrl->err);
+        if (e != ~0ull) {
+            result->status = (int32_t)(e & 15u);
+            result->count = e >> 4;
+        } else if (mode == kFinConvert) {
+            const u64 tot = ld_agent(&ctrl->total);
+            result->status = tot > out_cap ? (int32_t)kOutputTooSmall : (int32_t)kOk;
+            result->count = tot;
+        } else {
+            result->status = kOk;
+            result->count = n;
+        }
+        result->pad = 0;
     }
-    if (tid != 0) return;
-    const u64 e = ld_agent(&ctrl->err);
-    if (e != ~0ull) {
-        result->status = (int32_t)(e & 15u);
-        result->count = e >> 4;
-    } else if (mode == kFinConvert) {
-        const u64 tot = ld_agent(&ctrl->total);
-        result->status = tot > out_cap ? (int32_t)kOutputTooSmall : (int32_t)kOk;
-        result->count = tot;
-    } else {
-        result->status = kOk;
-        result->count = n;
-    }
-    result->pad = 0;
-    st_agent(&ctrl->err, ~0ull);
-    st_agent(&ctrl->total, 0);
-    st_agent(&ctrl->ticket, 0);
-    ctrl->bad = 0;
-    st_agent(&ctrl->epoch, wrap ? 1 : next);
+    reset_control(ctrl, tid, kBlock);   // its barrier orders the reads above before the reset
 }
 
 __global__ __launch_bounds__(kBlock) void ctrl_init_kernel(Ctrl *ctrl, u64 *status, u64 status_cap, u64 period) {
@@ -1295,6 +1283,7 @@ __global__ __launch_bounds__(kBlock) void ctrl_init_kernel(Ctrl *ctrl, u64 *stat
         ctrl->err = ~0ull;
         ctrl->total = 0;
         ctrl->ticket = 0;
+        ctrl->done = 0;
         ctrl->bad = 0;
         ctrl->epoch = 1;
         ctrl->period = period;
@@ -1402,11 +1391,9 @@ __device__ u64 batch_out_offset(const uint8_t *frame, long long head, long long 
 
 // Per string: output offsets, result, and the reset of its error word and
 // start bit for the next call.
-__global__ void batch_post_kernel(const uint8_t *frame, long long head, long long n, BatchCtx bc, Ctrl *ctrl,
-                                  int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
-                                  uint32_t *starts) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > bc.k) return;
+__device__ __forceinline__ void post_string(const uint8_t *frame, long long head, long long n, const BatchCtx &bc,
+                                            Ctrl *ctrl, int64_t *out_offsets, DevResult *results, u64 out_cap,
+                                            const uint32_t *bad, uint32_t *starts, u64 i) {
     const bool ok = *bad == 0;
     const u64 total = ld_agent(&ctrl->total);
     const int64_t a = bc.offsets[i];
@@ -1437,6 +1424,16 @@ __global__ void batch_post_kernel(const uint8_t *frame, long long head, long lon
     }
 }
 
+// Thread i <= k: string i's output offset and result (post_string); then
+// the last workgroup to finish resets the control block for the next call.
+__global__ void batch_post_kernel(const uint8_t *frame, long long head, long long n, BatchCtx bc, Ctrl *ctrl,
+                                  int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
+                                  uint32_t *starts) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= bc.k) post_string(frame, head, n, bc, ctrl, out_offsets, results, out_cap, bad, starts, i);
+    batch_call_done(ctrl, threadIdx.x);
+}
+
 // Mark the string starts and index the wave spans (both directions); the
 // offsets flag is cleared by the finalize kernel of the previous call.
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
@@ -1450,7 +1447,7 @@ hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long
 
 hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets, u64 k,
                              uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results, u64 *status,
-                             Ctrl *ctrl, DevResult *scratch_result, uint32_t *starts, uint16_t *blockoff,
+                             Ctrl *ctrl, uint32_t *starts, uint16_t *blockoff,
                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,
                              hipStream_t stream) {
     const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
@@ -1466,9 +1463,7 @@ hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, 
                            head, n, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
     hipLaunchKernelGGL(batch_post_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, n, bc, ctrl, out_offsets,
                        results, out_cap, (const uint32_t *)bad, starts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // reset the control block (error word unused here, total, epoch)
-    return launch_finalize(ctrl, scratch_result, nullptr, kFinConvert, (u64)n, out_cap, nullptr, 0, stream);
+    return hipGetLastError();
 }
 
 int partial_blocks(long long units, long long units_per_block) {

@@ -1,11 +1,13 @@
 """The call epoch that tags look-back status words wraps on the device:
-the finalize kernel of the call that reaches the epoch period clears every
-status word of its workspace.  With UTFGPU_EPOCH_PERIOD=3 (read once per
-process, so in a child process) the epoch wraps every second call; large
-calls that leave many status words, small calls, validate calls and
-replays of a captured graph are interleaved so that a stale word of an
-earlier call meets the current epoch at every offset of the cycle.  Every
-result must equal the oracle's."""
+the last kernel of the call that reaches the epoch period (the finalize
+kernel, or the post kernel of a batched call) clears every status word of
+its workspace.  With UTFGPU_EPOCH_PERIOD=3 (read once per process, so in a
+child process) the epoch wraps every second call; large calls that leave
+many status words, small calls, validate calls, batched calls in both
+directions and replays of a captured graph are interleaved so that a stale
+word of an earlier call meets the current epoch at every offset of the
+cycle, in block and in ticket tile order.  Every result must equal the
+oracle's."""
 import os
 import subprocess
 import sys
@@ -48,6 +50,42 @@ for n_small in range(7):
     st, cnt, back = G.convert_utf16le_to_utf8(u)
     assert (st, cnt) == (0, X.size) and np.array_equal(back[:cnt].cpu().numpy(), X), ("16to8", n_small)
 
+# batched calls (whose post kernel ends the call) between single-buffer calls
+from workloads.mixes import make_batch
+
+def check_batch(bt, enc, label):
+    k = bt.offsets.size - 1
+    offs = torch.from_numpy(bt.offsets).to("cuda")
+    oo = torch.empty(k + 1, dtype=torch.int64, device="cuda")
+    rs = G.results_tensor(k)
+    if enc == "utf-8":
+        d = torch.from_numpy(bt.data).to("cuda")
+        o = torch.empty(2 * bt.data.size, dtype=torch.int16, device="cuda")
+        assert G.convert_utf8_to_utf16le_batch_async(d, offs, o, oo, rs) == 0
+        ost, ocnt, oout, ooff = O.convert_utf8_to_utf16le_batch(bt.data, bt.offsets)
+        got = o.cpu().numpy().view(np.uint16)
+    else:
+        d = torch.from_numpy(bt.data.view(np.int16)).to("cuda")
+        o = torch.empty(3 * bt.data.size, dtype=torch.uint8, device="cuda")
+        assert G.convert_utf16le_to_utf8_batch_async(d, offs, o, oo, rs) == 0
+        ost, ocnt, oout, ooff = O.convert_utf16le_to_utf8_batch(bt.data, bt.offsets)
+        got = o.cpu().numpy()
+    torch.cuda.synchronize()
+    st, cnt = G.decode_results(rs, k)
+    assert np.array_equal(oo.cpu().numpy(), ooff), label
+    assert np.array_equal(st, ost) and np.array_equal(cnt, ocnt), label
+    valid = np.repeat(ost == O.OK, np.diff(ooff))
+    assert np.array_equal(got[:ooff[-1]][valid], oout[valid]), label
+
+b8 = make_batch(k=1500, seed=41, median=2000, sigma=1.0, lo=0, hi=50_000, error_fraction=0.05)
+b16 = make_batch(k=1500, seed=42, encoding="utf-16-le", median=2000, sigma=1.0, lo=0, hi=50_000, error_fraction=0.05)
+for rep in range(6):
+    check_batch(b8, "utf-8", ("batch8", rep))
+    for i in range(rep % 3):
+        assert G.convert_utf8_to_utf16le(dz, out=small)[:2] == (0, 4096)
+    check_batch(b16, "utf-16-le", ("batch16", rep))
+    check8(dx, X, out, ("x after batches", rep))
+
 # a captured call replayed past many wraps, eager calls on the same stream between replays
 s = torch.cuda.Stream()
 res = G.result_tensor()
@@ -73,8 +111,9 @@ print("epoch wrap ok", flush=True)
 '''
 
 
-def test_epoch_wrap_matches_oracle():
-    env = dict(os.environ, UTFGPU_EPOCH_PERIOD="3")
+@pytest.mark.parametrize("schedule", ["0", "1"], ids=["block", "ticket"])
+def test_epoch_wrap_matches_oracle(schedule):
+    env = dict(os.environ, UTFGPU_EPOCH_PERIOD="3", UTFGPU_SCHEDULE=schedule)
     r = subprocess.run([sys.executable, "-c", "ROOT_DIR = " + repr(ROOT) + "\n" + CHILD], env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]

@@ -34,9 +34,15 @@ for mix in ("mix1m", "cjk", "emoji", "ascii"):
         assert (st, cnt) == (0, b.size) and np.array_equal(back[:cnt].cpu().numpy(), b), (mix, size)
 # batched calls through the same path, both directions
 from workloads.mixes import make_batch
-for enc in ("utf-8", "utf-16-le"):
-    bt = make_batch(k=3000, seed=777, encoding=enc, median=300, sigma=1.5, lo=0, hi=200_000, error_fraction=0.05)
+# the last case is a batched UTF-16 call above 4 MiB, which the shipped
+# table runs in the 4 x 4 build
+for enc, kk, med in (("utf-8", 3000, 300), ("utf-16-le", 3000, 300), ("utf-16-le", 6000, 1200)):
+    bt = make_batch(k=kk, seed=777 + kk, encoding=enc, median=med, sigma=1.5, lo=0, hi=200_000, error_fraction=0.05)
     k = bt.offsets.size - 1
+    if kk == 6000:
+        nb = 2 * bt.data.size
+        assert nb > (4 << 20), nb
+        assert G.geometries()[G.get_geometry(G.OP_BATCH_UTF16LE, G.size_class(nb))][:2] == (4, 4)
     offs = torch.from_numpy(bt.offsets).to("cuda")
     oo = torch.empty(k + 1, dtype=torch.int64, device="cuda")
     rs = G.results_tensor(k)
