@@ -37,14 +37,13 @@
     hipError_t launch_set_u64(u64 *r, u64 v, hipStream_t stream);                                                 \
     hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, const int64_t *offsets,       \
                                  u64 k, uint16_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
-                                 u64 *status, Ctrl *ctrl, uint32_t *starts,            \
-                                 uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr,   \
-                                 int schedule, hipStream_t stream);                                               \
+                                 u64 *status, Ctrl *ctrl, uint32_t *starts, uint16_t *blockoff, u64 *tilepre,     \
+                                 u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule, hipStream_t stream);  \
     hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m, const int64_t *offsets,      \
                                   u64 k, uint8_t *out, u64 out_cap, int64_t *out_offsets, DevResult *results,     \
-                                  u64 *status, Ctrl *ctrl, uint32_t *starts,           \
-                                  uint16_t *blockoff, u64 *tilepre, u64 *serr, uint32_t *bad,                     \
-                                  uint32_t *wavestr, int schedule, hipStream_t stream);                           \
+                                  u64 *status, Ctrl *ctrl, uint32_t *starts, uint16_t *blockoff, u64 *tilepre,    \
+                                  u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,                      \
+                                  hipStream_t stream);                                                            \
     }                                                                                                             \
     }
 #include "geometries.def"
