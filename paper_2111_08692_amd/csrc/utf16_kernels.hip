@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
     LaneUnits t;
     load_span16(frame, head, end, wbase, lane, t);
-    const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
+    const u64 epoch = kConvert && wave == 0 ? ld_agent(&ctrl->epoch) : 0;   // only wave 0 looks back
     uint32_t width[kRows];
     uint32_t cls = survey16<kConvert>(t, wbase, head, end, lane, width);
     if (cls == kAscii16 && t.edge) cls = kUpTo2B;   // whole-chunk narrowing: not at the ends

@@ -1047,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const long long wbase = (long long)tile * kTileBytes + (long long)wave * kWaveBytes;
     LaneBytes t;
     issue_span(frame, end, wbase, lane, t);
-    const u64 epoch = kConvert ? ld_agent(&ctrl->epoch) : 0;
+    const u64 epoch = kConvert && wave == 0 ? ld_agent(&ctrl->epoch) : 0;   // only wave 0 looks back
     finish_span(head, end, wbase, lane, t);
     {
         Survey sv;
