@@ -31,8 +31,8 @@ from typing import List, Tuple
 import numpy as np
 import torch
 
-from . import (OK, convert_utf8_to_utf16le_async, convert_utf16le_to_utf8_async, decode_result, load,
-               result_tensor)
+from . import (OK, convert_utf8_to_utf16le, convert_utf8_to_utf16le_async, convert_utf16le_to_utf8,
+               convert_utf16le_to_utf8_async, decode_result, load, result_tensor)
 
 
 def cuts_utf8(data: np.ndarray, chunk: int) -> List[int]:
@@ -175,19 +175,40 @@ class HostPipeline:
             si = (nchunks + k) % ns
             if out_pend[si] is not None:
                 finish_out(si)
+        if first_err is not None:
+            # the output of the valid prefix: the chunks before the failing
+            # one (already in place) and the failing chunk's valid part,
+            # converted again from its device input (its stream has run
+            # nothing after it)
+            ci, st, pos = first_err
+            si = ci % ns
+            k = pos - cuts[ci]   # valid units of the failing chunk
+            if k > 0:
+                s = self.streams[si]
+                with torch.cuda.stream(s):
+                    if to16:
+                        st2, cnt2, o = convert_utf8_to_utf16le(self.d_in[si][:k], stream=s)
+                    else:
+                        st2, cnt2, o = convert_utf16le_to_utf8(self.d_in[si][:2 * k].view(torch.int16), stream=s)
+                if st2 != OK:
+                    raise RuntimeError(f"the valid prefix of chunk {ci} did not convert: {st2}")
+                nb = cnt2 * out_unit
+                final_t[written:written + nb].copy_(o.view(torch.uint8)[:nb])
+                written += nb
         torch.cuda.synchronize(self.dev)
         self.last = {"seconds": time.perf_counter() - t0, "chunks": nchunks, "input_bytes": raw.size}
-        if first_err is not None:
-            return first_err[1], first_err[2], np.zeros(0, dtype=np.uint16 if to16 else np.uint8)
         out = final[:written]
         out = out.view(np.uint16) if to16 else out
+        if first_err is not None:
+            return first_err[1], first_err[2], out
         return OK, int(out.size), out
 
     def convert_utf8_to_utf16le(self, data: np.ndarray) -> Tuple[int, int, np.ndarray]:
         """Host uint8 array -> ``(status, count, uint16 array)``; on an error
-        ``(kind, first error, empty)``."""
+        ``(kind, first error, the words of the valid prefix)``."""
         return self._run(np.asarray(data, dtype=np.uint8), True)
 
     def convert_utf16le_to_utf8(self, data: np.ndarray) -> Tuple[int, int, np.ndarray]:
-        """Host uint16 array -> ``(status, count, uint8 array)``."""
+        """Host uint16 array -> ``(status, count, uint8 array)``; on an error
+        ``(kind, first error, the bytes of the valid prefix)``."""
         return self._run(np.asarray(data, dtype=np.uint16), False)
