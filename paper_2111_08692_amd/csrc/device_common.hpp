@@ -377,6 +377,9 @@ __device__ __forceinline__ void reset_control(Ctrl *ctrl, uint32_t tid, uint32_t
     st_agent(&ctrl->epoch, wrap ? 1 : next);
 }
 
+// Threads per workgroup of the batched calls' post kernels.
+constexpr uint32_t kPostBlock = 256;
+
 // Batched calls end in their post kernel: every workgroup counts itself
 // done once its threads have read what they need of the control block, and
 // the last one resets it (so no separate finalize launch is needed).
@@ -409,9 +412,11 @@ struct BatchCtx {
 
 // The string that owns input unit p: the largest i with offsets[i] <= p
 // (an empty string owns no byte, and is never the largest such i).
-// Binary search in [lo, hi).
+// Binary search in [lo, hi); returns lo at once when hi <= lo + 1 (which
+// offsets that are not a partition can produce: such a call reports
+// ERR_OFFSETS for every string, and the search only has to end).
 __device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 lo, u64 hi, long long p) {
-    while (hi - lo > 1) {
+    while (hi > lo + 1) {
         const u64 mid = (lo + hi) / 2;
         if (offsets[mid] <= p) lo = mid;
         else hi = mid;
@@ -420,11 +425,16 @@ __device__ __forceinline__ u64 owner_string(const int64_t *offsets, u64 lo, u64 
 }
 
 // The owner of input unit p lying in wave span w or in the three units
-// before it: between the owners of spans w-1 and w+1.
+// before it: between the owners of spans w-1 and w+1.  The span owners are
+// clamped to [0, k): with offsets that are not a partition some spans have
+// no owner and keep a value from an earlier call.
 __device__ __forceinline__ u64 owner_near(const BatchCtx &bc, long long w, long long p) {
-    const u64 lo = bc.wavestr[w > 0 ? w - 1 : 0];
-    const u64 hi1 = (u64)bc.wavestr[w + 1] + 1;
-    return owner_string(bc.offsets, lo, hi1 < bc.k ? hi1 : bc.k, p);
+    const u64 last = bc.k - 1;   // k >= 1 whenever a tile kernel runs
+    u64 lo = bc.wavestr[w > 0 ? w - 1 : 0];
+    u64 hi1 = (u64)bc.wavestr[w + 1] + 1;
+    lo = lo < last ? lo : last;
+    hi1 = hi1 < bc.k ? hi1 : bc.k;
+    return owner_string(bc.offsets, lo, hi1, p);
 }
 
 // ------------------------------------------------------------------------

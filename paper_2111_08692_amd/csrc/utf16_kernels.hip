@@ -721,13 +721,10 @@ __device__ u64 batch_out_offset16(const uint8_t *frame, long long head, long lon
 
 // Per string: output offsets, result, and the reset of its error word and
 // start bit for the next call.
-__device__ __forceinline__ void post_string16(const uint8_t *frame, long long head, long long m, const BatchCtx &bc,
-                                              Ctrl *ctrl, int64_t *out_offsets, DevResult *results, u64 out_cap,
-                                              const uint32_t *bad, uint32_t *starts, u64 i) {
-    const bool ok = *bad == 0;
-    const u64 total = ld_agent(&ctrl->total);
+__device__ __forceinline__ void post_string16(const BatchCtx &bc, long long m, int64_t *out_offsets,
+                                              DevResult *results, u64 out_cap, bool ok, uint32_t *starts,
+                                              long long head, u64 i, u64 oa, u64 ob) {
     const int64_t a = bc.offsets[i];
-    const u64 oa = ok ? batch_out_offset16(frame, head, m, bc, total, a) : 0;
     out_offsets[i] = (int64_t)oa;
     if (i == bc.k) return;
     const int64_t b = bc.offsets[i + 1];
@@ -743,7 +740,6 @@ __device__ __forceinline__ void post_string16(const uint8_t *frame, long long he
         results[i].count = 0;
         return;
     }
-    const u64 ob = batch_out_offset16(frame, head, m, bc, total, b);
     if (e != ~0ull) {
         results[i].status = (int32_t)(e & 15u);
         results[i].count = e >> 4;
@@ -753,14 +749,29 @@ __device__ __forceinline__ void post_string16(const uint8_t *frame, long long he
     }
 }
 
-// Thread i <= k: string i's output offset and result; then the last
-// workgroup to finish resets the control block for the next call.
-__global__ void batch_post16_kernel(const uint8_t *frame, long long head, long long m, BatchCtx bc, Ctrl *ctrl,
-                                    int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
-                                    uint32_t *starts) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= bc.k) post_string16(frame, head, m, bc, ctrl, out_offsets, results, out_cap, bad, starts, i);
-    batch_call_done(ctrl, threadIdx.x);
+// Thread i <= k: the output offset at offsets[i], shared through LDS (the
+// workgroup's last thread also computes the one after its string); then
+// string i's offsets and result, and the last workgroup to finish resets
+// the control block for the next call.  kPostBlock threads per workgroup.
+__global__ __launch_bounds__(kPostBlock) void batch_post16_kernel(const uint8_t *frame, long long head, long long m,
+                                                                  BatchCtx bc, Ctrl *ctrl, int64_t *out_offsets,
+                                                                  DevResult *results, u64 out_cap,
+                                                                  const uint32_t *bad, uint32_t *starts) {
+    __shared__ u64 s_off[kPostBlock + 1];
+    const uint32_t tid = threadIdx.x;
+    const u64 i = (u64)blockIdx.x * kPostBlock + tid;
+    const bool ok = *bad == 0;
+    const u64 total = ld_agent(&ctrl->total);
+    if (i <= bc.k) {
+        s_off[tid] = ok ? batch_out_offset16(frame, head, m, bc, total, bc.offsets[i]) : 0;
+        if (tid == kPostBlock - 1 && i < bc.k)
+            s_off[kPostBlock] = ok ? batch_out_offset16(frame, head, m, bc, total, bc.offsets[i + 1]) : 0;
+    }
+    __syncthreads();
+    if (i <= bc.k)
+        post_string16(bc, m, out_offsets, results, out_cap, ok, starts, head, i, s_off[tid],
+                      i < bc.k ? s_off[tid + 1] : 0);
+    batch_call_done(ctrl, tid);
 }
 
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
@@ -781,7 +792,7 @@ hipError_t launch_utf16_batch(const uint8_t *frame, long long head, long long m,
     else if (m > 0)
         hipLaunchKernelGGL((utf16_tile_kernel<true, true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, stream, frame,
                            head, m, out, out_cap, status, ctrl, ntiles, lookback_spin_limit(), bc);
-    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    const unsigned pb = kPostBlock, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(batch_post16_kernel, dim3(pg), dim3(pb), 0, stream, frame, head, m, bc, ctrl, out_offsets,
                        results, out_cap, (const uint32_t *)bad, starts);
     return hipGetLastError();

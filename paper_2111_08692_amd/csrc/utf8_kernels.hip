@@ -1340,21 +1340,17 @@ hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head,
 // ------------------------------------------------------------------------
 // Batched UTF-8 -> UTF-16LE
 // ------------------------------------------------------------------------
-// Thread i <= k marks the first byte of string i (when non-empty) in the
-// start bitmap and checks the offsets (0 = offsets[0] <= ... <= offsets[k]
-// = n); a bad array sets `bad` (a word of the control block, zero between
-// calls) and marks nothing for the strings it concerns.  Thread w <= nspans
-// records the string owning the first position of wave span w (`span`
-// units, frame coordinates), so that an error's owner is found among the
-// few strings near its wave.  One launch does both.
+// Thread i < k checks string i's offsets (0 = offsets[0] <= ... <=
+// offsets[k] = n; a bad array sets `bad`, a word of the control block that
+// is zero between calls), marks its first byte in the start bitmap when it
+// is not empty, and records it as the owner of every wave span (`span`
+// units, frame coordinates) whose first position it holds; positions before
+// the input count as position 0 and positions past it as position n - 1.
+// So an error's owner is found among the few strings near its wave, and no
+// thread searches.  Thread k checks the last offset.
 __global__ void batch_prep_kernel(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
                                   uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans) {
     const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= nspans) {
-        long long p = (long long)i * span - head;
-        p = p < 0 ? 0 : (p >= n ? n - 1 : p);
-        wavestr[i] = (uint32_t)owner_string(offsets, 0, k, p);
-    }
     if (i > k) return;
     const int64_t a = offsets[i];
     if (i == 0 && a != 0) atomicOr(bad, 1u);
@@ -1367,10 +1363,12 @@ __global__ void batch_prep_kernel(const int64_t *offsets, u64 k, long long head,
         atomicOr(bad, 1u);
         return;
     }
-    if (b > a) {
-        const u64 q = (u64)(head + a);
-        atomicOr(starts + (q >> 5), 1u << (q & 31u));
-    }
+    if (b == a) return;
+    const u64 q = (u64)(head + a);
+    atomicOr(starts + (q >> 5), 1u << (q & 31u));
+    const long long wlo = a == 0 ? 0 : (a + head + span - 1) / span;
+    const long long whi = b == n ? (long long)nspans : (b + head + span - 1) / span - 1;
+    for (long long w = wlo; w <= whi; ++w) wavestr[w] = (uint32_t)i;
 }
 
 // Output offset of input byte p: the tile's offset, the offset of p's
@@ -1390,14 +1388,12 @@ __device__ u64 batch_out_offset(const uint8_t *frame, long long head, long long 
 }
 
 // Per string: output offsets, result, and the reset of its error word and
-// start bit for the next call.
-__device__ __forceinline__ void post_string(const uint8_t *frame, long long head, long long n, const BatchCtx &bc,
-                                            Ctrl *ctrl, int64_t *out_offsets, DevResult *results, u64 out_cap,
-                                            const uint32_t *bad, uint32_t *starts, u64 i) {
-    const bool ok = *bad == 0;
-    const u64 total = ld_agent(&ctrl->total);
+// start bit for the next call.  `oa` and `ob` are the output offsets at the
+// string's first and past its last position (0 when the offsets are bad).
+__device__ __forceinline__ void post_string(const BatchCtx &bc, long long n, int64_t *out_offsets,
+                                            DevResult *results, u64 out_cap, bool ok, uint32_t *starts,
+                                            long long head, u64 i, u64 oa, u64 ob) {
     const int64_t a = bc.offsets[i];
-    const u64 oa = ok ? batch_out_offset(frame, head, n, bc, total, a) : 0;
     out_offsets[i] = (int64_t)oa;
     if (i == bc.k) return;
     const int64_t b = bc.offsets[i + 1];
@@ -1414,7 +1410,6 @@ __device__ __forceinline__ void post_string(const uint8_t *frame, long long head
         results[i].count = 0;
         return;
     }
-    const u64 ob = batch_out_offset(frame, head, n, bc, total, b);
     if (e != ~0ull) {
         results[i].status = (int32_t)(e & 15u);
         results[i].count = e >> 4;
@@ -1424,22 +1419,37 @@ __device__ __forceinline__ void post_string(const uint8_t *frame, long long head
     }
 }
 
-// Thread i <= k: string i's output offset and result (post_string); then
-// the last workgroup to finish resets the control block for the next call.
-__global__ void batch_post_kernel(const uint8_t *frame, long long head, long long n, BatchCtx bc, Ctrl *ctrl,
-                                  int64_t *out_offsets, DevResult *results, u64 out_cap, const uint32_t *bad,
-                                  uint32_t *starts) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= bc.k) post_string(frame, head, n, bc, ctrl, out_offsets, results, out_cap, bad, starts, i);
-    batch_call_done(ctrl, threadIdx.x);
+// Thread i <= k: the output offset at offsets[i], shared through LDS so
+// that each offset is computed once (the workgroup's last thread also
+// computes the one after its string); then string i's offsets and result
+// (post_string), and the last workgroup to finish resets the control block
+// for the next call.  Launched with kPostBlock threads per workgroup.
+__global__ __launch_bounds__(kPostBlock) void batch_post_kernel(const uint8_t *frame, long long head, long long n,
+                                                                BatchCtx bc, Ctrl *ctrl, int64_t *out_offsets,
+                                                                DevResult *results, u64 out_cap,
+                                                                const uint32_t *bad, uint32_t *starts) {
+    __shared__ u64 s_off[kPostBlock + 1];
+    const uint32_t tid = threadIdx.x;
+    const u64 i = (u64)blockIdx.x * kPostBlock + tid;
+    const bool ok = *bad == 0;
+    const u64 total = ld_agent(&ctrl->total);
+    if (i <= bc.k) {
+        s_off[tid] = ok ? batch_out_offset(frame, head, n, bc, total, bc.offsets[i]) : 0;
+        if (tid == kPostBlock - 1 && i < bc.k)
+            s_off[kPostBlock] = ok ? batch_out_offset(frame, head, n, bc, total, bc.offsets[i + 1]) : 0;
+    }
+    __syncthreads();
+    if (i <= bc.k)
+        post_string(bc, n, out_offsets, results, out_cap, ok, starts, head, i, s_off[tid],
+                    i < bc.k ? s_off[tid + 1] : 0);
+    batch_call_done(ctrl, tid);
 }
 
 // Mark the string starts and index the wave spans (both directions); the
-// offsets flag is cleared by the finalize kernel of the previous call.
+// offsets flag is cleared at the end of the previous call.
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
                              uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream) {
-    const u64 threads = (k > nspans ? k : nspans) + 1;
-    const unsigned pb = 256, pg = (unsigned)((threads + pb - 1) / pb);
+    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad, span,
                        wavestr, nspans);
     return hipGetLastError();
@@ -1450,7 +1460,7 @@ hipError_t launch_utf8_batch(const uint8_t *frame, long long head, long long n, 
                              Ctrl *ctrl, uint32_t *starts, uint16_t *blockoff,
                              u64 *tilepre, u64 *serr, uint32_t *bad, uint32_t *wavestr, int schedule,
                              hipStream_t stream) {
-    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    const unsigned pb = kPostBlock, pg = (unsigned)((k + 1 + pb - 1) / pb);
     const u64 ntiles = utf8_tiles_for(head, n);
     hipError_t e = launch_batch_prep(offsets, k, head, n, starts, bad, kWaveBytes, wavestr, ntiles * kWaves, stream);
     if (e != hipSuccess) return e;

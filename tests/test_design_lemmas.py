@@ -534,3 +534,56 @@ def test_weighted_sums_value_flags_match_the_rules(orc, lead):
     data = np.stack([(w >> (8 * k)) & 0xFF for k in range(L)], axis=1).astype(np.uint8).reshape(-1)
     st, _ = orc.validate_utf8_batch(data, np.arange(0, data.size + 1, L, dtype=np.int64))
     assert np.array_equal(bad, st != O.OK)
+
+
+# ---------------------------------------------------------------------------
+# Batched calls: the owner of every wave span without a search.  The span
+# owner is defined as the largest i with offsets[i] <= p for the span's first
+# position p (clamped to [0, n - 1]), i.e. a binary search; the prep kernel
+# instead lets string i write itself into every span w whose first position
+# it holds: w from ceil((a + head) / span) (from 0 when a = 0) to
+# ceil((b + head) / span) - 1 (to the last span when b = n).  For offsets
+# that partition [0, n] the two agree on every span.
+# ---------------------------------------------------------------------------
+def _owner_by_search(offsets, p):
+    lo, hi = 0, len(offsets) - 1
+    while hi > lo + 1:
+        mid = (lo + hi) // 2
+        if offsets[mid] <= p:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def _owners_by_strings(offsets, head, span, nspans):
+    n = offsets[-1]
+    own = [None] * (nspans + 1)
+    for i in range(len(offsets) - 1):
+        a, b = offsets[i], offsets[i + 1]
+        if a == b:
+            continue
+        wlo = 0 if a == 0 else (a + head + span - 1) // span
+        whi = nspans if b == n else (b + head + span - 1) // span - 1
+        for w in range(wlo, whi + 1):
+            own[w] = i
+    return own
+
+
+def test_span_owners_without_search():
+    rng = np.random.default_rng(17)
+    for _ in range(4000):
+        k = int(rng.integers(1, 40))
+        lens = rng.integers(0, 300, size=k) * (rng.random(k) < 0.8)
+        if lens.sum() == 0:
+            lens[int(rng.integers(0, k))] = int(rng.integers(1, 50))
+        offsets = [0] + np.cumsum(lens).astype(int).tolist()
+        n = offsets[-1]
+        head = int(rng.integers(0, 16))
+        span = int(rng.choice([16, 64, 128, 2048]))
+        nspans = 4 * ((head + n + 4 * span - 1) // (4 * span))
+        want = []
+        for w in range(nspans + 1):
+            p = min(max(w * span - head, 0), n - 1)
+            want.append(_owner_by_search(offsets, p))
+        assert _owners_by_strings(offsets, head, span, nspans) == want, (offsets, head, span)

@@ -195,6 +195,29 @@ def test_bad_offsets_then_good_call(G, orc):
     assert k == 500
 
 
+def test_scrambled_offsets_over_invalid_bytes(G, orc):
+    """Offsets that are not a partition, over bytes full of errors: flagged
+    waves look up the owners of their errors in span owners that the bad
+    offsets leave unset (or set by an earlier call with many more strings);
+    every string reports ERR_OFFSETS and the library is clean afterwards."""
+    rng = np.random.default_rng(91)
+    data = rng.integers(0, 256, size=3 << 20, dtype=np.uint8)
+    n = data.size
+    many = np.r_[0, np.sort(rng.integers(0, n, size=19_999)), n].astype(np.int64)   # valid, 20 000 strings
+    check_batch(G, orc, data, many, label="many strings first")
+    for k in (50, 3000):
+        bad = rng.integers(0, n, size=k + 1).astype(np.int64)   # unsorted
+        bad[0], bad[-1] = 0, n
+        rc, st, cnt, goff, *_ = run_batch(G, data, bad, cap=n)
+        assert rc == 0 and np.all(st == G.ERR_OFFSETS) and np.all(cnt == 0) and np.all(goff == 0), k
+        d16 = rng.integers(0xD000, 0xE000, size=n // 2).astype(np.uint16)
+        bad16 = rng.integers(0, n // 2, size=k + 1).astype(np.int64)
+        bad16[0], bad16[-1] = 0, n // 2
+        rc, st, cnt, goff, *_ = run_batch16(G, d16, bad16, cap=3 * d16.size)
+        assert rc == 0 and np.all(st == G.ERR_OFFSETS) and np.all(goff == 0), k
+    check_batch(G, orc, data, many, label="many strings after")
+
+
 def test_full_size_batch(G, orc):
     """100 000 strings, log-normal lengths (median 256 bytes, sigma 1.5,
     16 B .. 1 MiB), one script mix each, 1% with one injected error."""
