@@ -377,7 +377,9 @@ __device__ __forceinline__ void reset_control(Ctrl *ctrl, uint32_t tid, uint32_t
     st_agent(&ctrl->epoch, wrap ? 1 : next);
 }
 
-// Threads per workgroup of the batched calls' post kernels.
+// Threads per workgroup of the batched calls' prep and post kernels
+// (multiples of the wave size).
+constexpr uint32_t kPrepBlock = 256;
 constexpr uint32_t kPostBlock = 256;
 
 // Batched calls end in their post kernel: every workgroup counts itself

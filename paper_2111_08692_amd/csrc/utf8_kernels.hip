@@ -1343,32 +1343,46 @@ hipError_t launch_utf8_tiles(bool convert, const uint8_t *frame, long long head,
 // Thread i < k checks string i's offsets (0 = offsets[0] <= ... <=
 // offsets[k] = n; a bad array sets `bad`, a word of the control block that
 // is zero between calls), marks its first byte in the start bitmap when it
-// is not empty, and records it as the owner of every wave span (`span`
-// units, frame coordinates) whose first position it holds; positions before
-// the input count as position 0 and positions past it as position n - 1.
-// So an error's owner is found among the few strings near its wave, and no
-// thread searches.  Thread k checks the last offset.
-__global__ void batch_prep_kernel(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
-                                  uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > k) return;
-    const int64_t a = offsets[i];
-    if (i == 0 && a != 0) atomicOr(bad, 1u);
-    if (i == k) {
-        if (a != n) atomicOr(bad, 1u);
-        return;
+// is not empty, and owns every wave span (`span` units, frame coordinates)
+// whose first position the string holds; positions before the input count
+// as position 0 and positions past it as position n - 1.  So an error's
+// owner is found among the few strings near its wave, and no thread
+// searches.  The 64 threads of a wave then write the owners of all their
+// strings' spans together (a string of many spans takes one store per lane
+// per 64 spans).  Thread k checks the last offset.  kPrepBlock threads per
+// workgroup.
+__global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(const int64_t *offsets, u64 k, long long head,
+                                                                long long n, uint32_t *starts, uint32_t *bad,
+                                                                long long span, uint32_t *wavestr, u64 nspans) {
+    const u64 i = (u64)blockIdx.x * kPrepBlock + threadIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    long long wlo = 1, whi = 0;   // the spans string i owns (none)
+    if (i <= k) {
+        const int64_t a = offsets[i];
+        if (i == 0 && a != 0) atomicOr(bad, 1u);
+        if (i == k) {
+            if (a != n) atomicOr(bad, 1u);
+        } else {
+            const int64_t b = offsets[i + 1];
+            if (a < 0 || b < a || b > n) {
+                atomicOr(bad, 1u);
+            } else if (b > a) {
+                const u64 q = (u64)(head + a);
+                atomicOr(starts + (q >> 5), 1u << (q & 31u));
+                wlo = a == 0 ? 0 : (a + head + span - 1) / span;
+                whi = b == n ? (long long)nspans : (b + head + span - 1) / span - 1;
+            }
+        }
     }
-    const int64_t b = offsets[i + 1];
-    if (a < 0 || b < a || b > n) {
-        atomicOr(bad, 1u);
-        return;
+#pragma unroll 1
+    for (int L = 0; L < kWave; ++L) {   // every lane of the wave takes part
+        const long long lo = (long long)(((u64)readlane((uint32_t)((u64)wlo >> 32), L) << 32) |
+                                         readlane((uint32_t)wlo, L));
+        const long long hi = (long long)(((u64)readlane((uint32_t)((u64)whi >> 32), L) << 32) |
+                                         readlane((uint32_t)whi, L));
+        const uint32_t owner = readlane((uint32_t)i, L);
+        for (long long w = lo + lane; w <= hi; w += kWave) wavestr[w] = owner;
     }
-    if (b == a) return;
-    const u64 q = (u64)(head + a);
-    atomicOr(starts + (q >> 5), 1u << (q & 31u));
-    const long long wlo = a == 0 ? 0 : (a + head + span - 1) / span;
-    const long long whi = b == n ? (long long)nspans : (b + head + span - 1) / span - 1;
-    for (long long w = wlo; w <= whi; ++w) wavestr[w] = (uint32_t)i;
 }
 
 // Output offset of input byte p: the tile's offset, the offset of p's
@@ -1449,7 +1463,7 @@ __global__ __launch_bounds__(kPostBlock) void batch_post_kernel(const uint8_t *f
 // offsets flag is cleared at the end of the previous call.
 hipError_t launch_batch_prep(const int64_t *offsets, u64 k, long long head, long long n, uint32_t *starts,
                              uint32_t *bad, long long span, uint32_t *wavestr, u64 nspans, hipStream_t stream) {
-    const unsigned pb = 256, pg = (unsigned)((k + 1 + pb - 1) / pb);
+    const unsigned pb = kPrepBlock, pg = (unsigned)((k + 1 + pb - 1) / pb);
     hipLaunchKernelGGL(batch_prep_kernel, dim3(pg), dim3(pb), 0, stream, offsets, k, head, n, starts, bad, span,
                        wavestr, nspans);
     return hipGetLastError();
