@@ -211,10 +211,10 @@ struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
     Ctrl *ctrl = nullptr;        // device
-    DevResult *dres = nullptr;   // device result slot
-    u64 *dlen = nullptr;         // device length slot
-    DevResult *hres = nullptr;   // pinned host copy
-    u64 *hlen = nullptr;         // pinned host copy
+    DevResult *hres = nullptr;   // pinned host result slot of the synchronous calls
+    u64 *hlen = nullptr;         // pinned host length slot
+    DevResult *dres = nullptr;   // the same slots as device addresses
+    u64 *dlen = nullptr;
     u64 *partials = nullptr;     // device partial sums of the length reductions
     u64 *status = nullptr;       // device tile status words
     u64 status_cap = 0;
@@ -236,8 +236,6 @@ std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 void free_ws(Workspace *w) {
     if (w->ctrl) (void)hipFree(w->ctrl);
-    if (w->dres) (void)hipFree(w->dres);
-    if (w->dlen) (void)hipFree(w->dlen);
     if (w->status) (void)hipFree(w->status);
     if (w->partials) (void)hipFree(w->partials);
     if (w->hres) (void)hipHostFree(w->hres);
@@ -256,11 +254,13 @@ hipError_t make_ws(int dev, hipStream_t s, Workspace **out) {
     w->stream = s;
     hipError_t e;
     if ((e = hipMalloc(&w->ctrl, sizeof(Ctrl))) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&w->dres, sizeof(DevResult))) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&w->dlen, sizeof(u64))) != hipSuccess) goto fail;
     if ((e = hipMalloc(&w->partials, kMaxPartials * sizeof(u64))) != hipSuccess) goto fail;
-    if ((e = hipHostMalloc(&w->hres, sizeof(DevResult), hipHostMallocDefault)) != hipSuccess) goto fail;
-    if ((e = hipHostMalloc(&w->hlen, sizeof(u64), hipHostMallocDefault)) != hipSuccess) goto fail;
+    // the synchronous calls' results: pinned, coherent host memory that the
+    // finalize kernel writes directly (no device-to-host copy per call)
+    if ((e = hipHostMalloc(&w->hres, sizeof(DevResult), hipHostMallocCoherent)) != hipSuccess) goto fail;
+    if ((e = hipHostMalloc(&w->hlen, sizeof(u64), hipHostMallocCoherent)) != hipSuccess) goto fail;
+    if ((e = hipHostGetDevicePointer((void **)&w->dres, w->hres, 0)) != hipSuccess) goto fail;
+    if ((e = hipHostGetDevicePointer((void **)&w->dlen, w->hlen, 0)) != hipSuccess) goto fail;
     if ((e = base::launch_ctrl_init(w->ctrl, nullptr, 0, epoch_period(), s)) != hipSuccess) goto fail;
     *out = w;
     return hipSuccess;
@@ -440,17 +440,17 @@ hipError_t noalloc_scratch(hipStream_t s, u64 **out) {
     return hipSuccess;
 }
 
+// The result of the call just queued on `s`: its finalize kernel writes it
+// straight into the workspace's pinned host slot.
 utf_result read_result(Workspace *w, hipStream_t s) {
-    if (hipMemcpyAsync(w->hres, w->dres, sizeof(DevResult), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return mk(UTF_ERR_HIP, 0);
     if (hipStreamSynchronize(s) != hipSuccess) return mk(UTF_ERR_HIP, 0);
-    return mk(w->hres->status, w->hres->count);
+    const volatile DevResult *r = w->hres;
+    return mk(r->status, r->count);
 }
 
 u64 read_len(Workspace *w, hipStream_t s) {
-    if (hipMemcpyAsync(w->hlen, w->dlen, sizeof(u64), hipMemcpyDeviceToHost, s) != hipSuccess) return ~0ull;
     if (hipStreamSynchronize(s) != hipSuccess) return ~0ull;
-    return *w->hlen;
+    return *(const volatile u64 *)w->hlen;
 }
 
 }  // namespace
