@@ -533,7 +533,7 @@ __device__ __forceinline__ void write_out_aligned(uint8_t *g0p, u64 nbytes, cons
 // blocks of global memory (the row's first byte g0 at stage byte g0 & 15).
 // The last block of a row is usually shared with the next row, so it is
 // not written but carried (16 bytes, the same in every lane) into the next
-// row's stage, whose block 0 it completes.  Only the wave's first and last
+// row, whose block 0 it completes in registers.  Only the wave's first and last
 // blocks are written in part; those take at most eight aligned stores of
 // 1/2/4/8 bytes (never below the unit size).
 struct Carry {
@@ -568,53 +568,75 @@ __device__ __forceinline__ void store_part(uintptr_t c, uintptr_t a, uintptr_t b
     }
 }
 
-// Merge the carried block into block 0 of the next row's stage: its bytes
-// before g0 & 15 come from the carry.  Lane 0; an LDS sync follows.
-__device__ __forceinline__ void merge_carry(uint32_t *stage, uintptr_t g0, const Carry &cy, uint32_t lane) {
-    const uint32_t k = (uint32_t)(g0 & 15u);
-    if (lane == 0 && k != 0) {
-        u32x4 b = *(const u32x4 *)stage;
-        uint32_t m[4];
+// Block 0 of a row whose first byte is at g0 & 15 = k (1..15): its bytes
+// before k come from the carried block.  Wave-uniform k: scalar masks.
+__device__ __forceinline__ u32x4 blend_carry(u32x4 b, const Carry &cy, uint32_t k) {
+    uint32_t m[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int lo = 4 * i;
-            m[i] = (int)k >= lo + 4 ? 0xFFFFFFFFu : ((int)k <= lo ? 0u : ((1u << (8 * ((int)k - lo))) - 1u));
-        }
-        b.x = (cy.v[0] & m[0]) | (b.x & ~m[0]);
-        b.y = (cy.v[1] & m[1]) | (b.y & ~m[1]);
-        b.z = (cy.v[2] & m[2]) | (b.z & ~m[2]);
-        b.w = (cy.v[3] & m[3]) | (b.w & ~m[3]);
-        *(u32x4 *)stage = b;
+    for (int i = 0; i < 4; ++i) {
+        const int lo = 4 * i;
+        m[i] = (int)k >= lo + 4 ? 0xFFFFFFFFu : ((int)k <= lo ? 0u : ((1u << (8 * ((int)k - lo))) - 1u));
     }
+    b.x = (cy.v[0] & m[0]) | (b.x & ~m[0]);
+    b.y = (cy.v[1] & m[1]) | (b.y & ~m[1]);
+    b.z = (cy.v[2] & m[2]) | (b.z & ~m[2]);
+    b.w = (cy.v[3] & m[3]) | (b.w & ~m[3]);
+    return b;
 }
 
 // Write a row's output [g0, g1) except its unfinished last block, which
 // goes to `cy`; bytes before `wstart` (the wave's first output byte) are
-// never written.  Whole wave; the stage holds the row, its block 0 merged
-// with the previous row's carry.
-template <int kUnit>
-__device__ __forceinline__ void write_row(uintptr_t g0, uintptr_t g1, uintptr_t wstart, const uint32_t *stage,
-                                          uint32_t lane, Carry &cy) {
+// never written.  Whole wave, after an LDS sync; the stage holds the row.
+// `merge`: the previous row's carried block ends at g0, so block 0 takes
+// its bytes before g0 (in registers, on its way to memory or to the next
+// carry).  Lane i stores blocks i, i + 64, ...: the first kIters of them
+// are read from LDS together and then stored, so the reads' latency is
+// paid once per row; a row of more blocks (not produced by the callers'
+// stage sizes) finishes in a plain loop.
+template <int kUnit, int kIters>
+__device__ __forceinline__ void write_row(uintptr_t g0, uintptr_t g1, uintptr_t wstart, uint32_t *stage,
+                                          uint32_t lane, Carry &cy, bool merge) {
     const uintptr_t c0 = g0 & ~(uintptr_t)15;
-    const uintptr_t lo = c0 > wstart ? c0 : wstart;
+    const uintptr_t lo = c0 > wstart ? c0 : wstart;   // lo < c0 + 16
     const uintptr_t hi = g1 & ~(uintptr_t)15;
+    const uint32_t k = (uint32_t)(g0 & 15u);
+    merge = merge && k != 0;
     const uint8_t *sb = (const uint8_t *)stage;
-    if (hi > lo) {
-        for (uintptr_t c = c0 + 16 * (uintptr_t)lane; c < hi; c += 16 * kWave) {
-            const uint32_t so = (uint32_t)(c - c0);
-            if (c >= lo)
-                __builtin_nontemporal_store(*(const u32x4 *)(sb + so), gptr<u32x4>(c));
-            else
-                store_part<kUnit>(c, lo, c + 16, sb, so);
-        }
+    const uint32_t nb = (uint32_t)((hi - c0) >> 4);   // blocks before the carried one
+    const bool part0 = c0 < lo;                       // block 0 begins before the wave's bytes
+    u32x4 v[kIters];
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+        const uint32_t b = lane + (uint32_t)(kWave * i);
+        v[i] = b < nb ? *(const u32x4 *)(sb + 16u * b) : u32x4{0u, 0u, 0u, 0u};
+    }
+    if (merge && lane == 0) v[0] = blend_carry(v[0], cy, k);
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+        const uint32_t b = lane + (uint32_t)(kWave * i);
+        if (b < nb && (b != 0 || !part0)) __builtin_nontemporal_store(v[i], gptr<u32x4>(c0 + 16 * (uintptr_t)b));
+    }
+    for (uint32_t b = lane + (uint32_t)(kWave * kIters); b < nb; b += kWave)
+        __builtin_nontemporal_store(*(const u32x4 *)(sb + 16u * b), gptr<u32x4>(c0 + 16 * (uintptr_t)b));
+    if (part0 && nb != 0 && lane == 0) {   // bytes [lo, c0 + 16) of block 0, through the stage
+        *(u32x4 *)stage = v[0];
+        store_part<kUnit>(c0, lo, c0 + 16, sb, 0);
     }
     if (g1 & 15u) {   // every lane reads the same block; kept in scalar registers
-        const u32x4 b = *(const u32x4 *)(sb + (uint32_t)(hi - c0));
+        u32x4 b = *(const u32x4 *)(sb + (uint32_t)(hi - c0));
+        if (merge && nb == 0) b = blend_carry(b, cy, k);   // the carried block is block 0
         cy.v[0] = __builtin_amdgcn_readfirstlane(b.x);
         cy.v[1] = __builtin_amdgcn_readfirstlane(b.y);
         cy.v[2] = __builtin_amdgcn_readfirstlane(b.z);
         cy.v[3] = __builtin_amdgcn_readfirstlane(b.w);
     }
+}
+
+// Passes of write_row over a stage of kBytes bytes of output plus up to 15
+// bytes of block offset.
+template <int kBytes>
+constexpr int row_write_iters() {
+    return ((kBytes + 15) / 16 + kWave - 1) / kWave;
 }
 
 // The wave's last unfinished block: bytes [max(block, wstart), gend) from

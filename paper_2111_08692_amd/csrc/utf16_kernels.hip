@@ -36,6 +36,7 @@ constexpr int kTileUnits = kTileBytes / 2;     // 32768 words per tile
 // plus the stray bytes past its end
 constexpr int kStageBytes16 = 3 * kRowUnits + 32;
 constexpr int kStageWords16 = kStageBytes16 / 4;   // a multiple of 4: stages stay 16-byte aligned
+constexpr int kWriteIters16 = row_write_iters<3 * kRowUnits>();   // a row: at most three bytes per unit
 
 // Wave classes by the words present: ASCII only; below 0x800; ASCII and
 // surrogates only (e.g. English with emoji: two bytes per surrogate word);
@@ -634,9 +635,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                 }
             }
             wave_lds_sync();
-            if (gend > wstart) merge_carry(wst, g0, cy, lane);
-            wave_lds_sync();
-            write_row<1>(g0, g1, wstart, wst, lane, cy);
+            write_row<1, kWriteIters16>(g0, g1, wstart, wst, lane, cy, gend > wstart);
             gend = g1;
             wave_lds_sync();
         }

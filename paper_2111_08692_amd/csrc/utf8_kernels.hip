@@ -48,6 +48,7 @@ constexpr bool has4(uint32_t cls) { return cls >= kQuad; }
 // written over the windows, shifted by up to seven words.
 constexpr uint32_t kStageSlots = kGroup * kRowBytes + 8;
 constexpr int kStageWords = (int)kStageSlots + 8;   // one dword per slot, per wave
+constexpr int kWriteIters = row_write_iters<2 * (int)kStageSlots>();   // a row: at most kStageSlots words
 
 __device__ __forceinline__ bool is_cont(uint32_t b) { return (b & 0xC0u) == 0x80u; }
 
@@ -884,9 +885,7 @@ __device__ __forceinline__ bool convert_wave(const LaneBytes &t, const uint32_t 
         }
         if (u0 < u1) {
             wave_lds_sync();
-            if (gend == g0 && gend > wlo) merge_carry(wst, g0, cy, lane);
-            wave_lds_sync();
-            write_row<2>(g0, g1, wlo, wst, lane, cy);
+            write_row<2, kWriteIters>(g0, g1, wlo, wst, lane, cy, gend == g0 && gend > wlo);
             gend = g1;
         }
         wave_lds_sync();
