@@ -209,6 +209,29 @@ __device__ __forceinline__ uint32_t add_byte(uint32_t a, uint32_t b, int k) {
     return d;
 }
 
+// LDS byte address of a pointer into a __shared__ array, and LDS pointers
+// made from such addresses.  A running store address kept absolute (base
+// included) serves each store as its address register as it is; kept as
+// an offset from a wave's stage, every store would first add the base.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) T *lptr(uint32_t a) {
+    return (__attribute__((address_space(3))) T *)(uintptr_t)a;
+}
+
+// A constant in a scalar register.  VOP3 instructions such as v_perm_b32
+// take no literal operand on this target, so a constant selector held in
+// a vector register is rematerialised with a v_mov wherever the register
+// allocator has dropped it; made by s_mov, it costs no vector issue slot.
+template <uint32_t kV>
+__device__ __forceinline__ uint32_t sconst() {
+    uint32_t v;
+    asm("s_mov_b32 %0, %1" : "=s"(v) : "i"(kV));
+    return v;
+}
+
 // bytes k..k+3 of the 8-byte little-endian pair (lo, hi)
 __device__ __forceinline__ uint32_t window4(uint32_t lo, uint32_t hi, int k) {
     return k == 0 ? lo : __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)k);

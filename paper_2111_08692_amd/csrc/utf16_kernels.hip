@@ -380,15 +380,16 @@ __device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o
             if (q0 + j >= head && q0 + j < end) in |= 1u << j;
     }
     const uint32_t o0 = o;
+    uint32_t ao = lds_addr(st) + o;   // LDS address of the word's first byte
     uint32_t first = 0, nfirst = 0;   // the lane's first two output bytes
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         uint32_t b0, b1, b2, len;
         encode_word<kClass>(word_of(t, r, j, pv), word_of(t, r, j - 1, pv), b0, b1, b2, len);
         if (kEdge && !((in >> j) & 1u)) len = 0;
-        st[o] = (uint8_t)b0;
-        st[o + 1] = (uint8_t)b1;
-        if (kClass != kUpTo2B && kClass != kQuad16) st[o + 2] = (uint8_t)b2;   // at most two bytes a word there
+        *lptr<uint8_t>(ao) = (uint8_t)b0;
+        *lptr<uint8_t>(ao + 1) = (uint8_t)b1;
+        if (kClass != kUpTo2B && kClass != kQuad16) *lptr<uint8_t>(ao + 2) = (uint8_t)b2;   // at most two bytes a word there
         if (!kEdge) {
             if (j == 0) {
                 first = (b0 & 0xFFu) | ((b1 & 0xFFu) << 8);
@@ -405,7 +406,7 @@ __device__ __forceinline__ void encode_row(const LaneUnits &t, int r, uint32_t o
                 }
             }
         }
-        o += len;
+        ao += len;
     }
     if (!kEdge) nfirst = 2;   // every word has at least one byte
     wave_lds_sync();          // every lane's stores land before the rewrite

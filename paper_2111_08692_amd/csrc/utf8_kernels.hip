@@ -319,7 +319,8 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
                                             long long head, long long end, uint32_t lane) {
     uint8_t *sb = (uint8_t *)wst;
     constexpr uint32_t kLast = 4u * (kStageSlots - 2);   // invalid input may announce more slots
-    uint32_t o = 4u * gof;
+    const uint32_t base = lds_addr(wst), last = base + kLast;
+    uint32_t o = base + 4u * gof;   // LDS address of the slot
     const uint32_t nx_row = next_dword(t, r, lane);
     uint32_t lead0 = 0;
 #pragma unroll
@@ -336,11 +337,11 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t win = window4(x, nx, k);
-            const uint32_t a = has4(kClass) ? min(o, kLast) : o;
+            const uint32_t a = has4(kClass) ? min(o, last) : o;
             // the marked copy goes to the next slot for a four-byte leading
             // byte, else to this slot, where the plain window replaces it
-            if (has4(kClass)) *(uint32_t *)(sb + add_byte(a, mark, k)) = win ^ 0x70u;
-            *(uint32_t *)(sb + a) = win;
+            if (has4(kClass)) *lptr<uint32_t>(add_byte(a, mark, k)) = win ^ 0x70u;
+            *lptr<uint32_t>(a) = win;
             o = add_byte(o, step, k);
         }
     }
@@ -577,9 +578,11 @@ __device__ __forceinline__ void words2(uint32_t x, uint32_t nx, uint32_t &ce, ui
     const uint32_t p = x & ~(c0 >> 1) & 0x7F7F7F7Fu;           // payload of a leading byte
     const uint32_t q = __builtin_amdgcn_alignbyte(nx, x, 1) & 0x3F3F3F3Fu;   // payload of the next byte
     const uint32_t m = (c0 << 1) - (c0 >> 7);                  // 0xFF for the bytes C0..DF
-    const uint32_t pe = __builtin_amdgcn_perm(0u, p, 0x0c020c00u), qe = __builtin_amdgcn_perm(0u, q, 0x0c020c00u);
-    const uint32_t po = __builtin_amdgcn_perm(0u, p, 0x0c030c01u), qo = __builtin_amdgcn_perm(0u, q, 0x0c030c01u);
-    const uint32_t me = __builtin_amdgcn_perm(0u, m, 0x02020000u), mo = __builtin_amdgcn_perm(0u, m, 0x03030101u);
+    const uint32_t se = sconst<0x0c020c00u>(), so = sconst<0x0c030c01u>();
+    const uint32_t pe = __builtin_amdgcn_perm(0u, p, se), qe = __builtin_amdgcn_perm(0u, q, se);
+    const uint32_t po = __builtin_amdgcn_perm(0u, p, so), qo = __builtin_amdgcn_perm(0u, q, so);
+    const uint32_t me = __builtin_amdgcn_perm(0u, m, sconst<0x02020000u>()),
+                   mo = __builtin_amdgcn_perm(0u, m, sconst<0x03030101u>());
     ce = (me & ((pe << 6) | qe)) | (~me & pe);
     co = (mo & ((po << 6) | qo)) | (~mo & po);
 }
@@ -632,12 +635,13 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(
 template <uint32_t kSel, uint32_t kMaskSel>
 __device__ __forceinline__ void words4_half(uint32_t x, uint32_t y, uint32_t z, uint32_t w, uint32_t mf,
                                             uint32_t &hw, uint32_t &lw) {
-    const uint32_t a = __builtin_amdgcn_perm(0u, x, kSel), b = __builtin_amdgcn_perm(0u, y, kSel),
-                   c = __builtin_amdgcn_perm(0u, z, kSel), d = __builtin_amdgcn_perm(0u, w, kSel);
+    const uint32_t sel = sconst<kSel>();
+    const uint32_t a = __builtin_amdgcn_perm(0u, x, sel), b = __builtin_amdgcn_perm(0u, y, sel),
+                   c = __builtin_amdgcn_perm(0u, z, sel), d = __builtin_amdgcn_perm(0u, w, sel);
     const uint32_t hi = as_u32(as_h2(a) * (unsigned short)256 + as_h2(b) * (unsigned short)4 +
                                (as_h2(c) >> (unsigned short)4) + (unsigned short)0xE5B8);
     lw = as_u32(as_h2(c & 0x000F000Fu) * (unsigned short)64 + as_h2(d) + (unsigned short)0xDB80);
-    const uint32_t m = __builtin_amdgcn_perm(0u, mf, kMaskSel);
+    const uint32_t m = __builtin_amdgcn_perm(0u, mf, sconst<kMaskSel>());
     hw = (m & hi) | (~m & a);   // the byte itself at the other positions
 }
 
@@ -686,10 +690,9 @@ __device__ __forceinline__ bool quad_values_bad(const LaneBytes &t, uint32_t lan
 __device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, uint32_t lane,
                                              bool vals) {
     uint16_t *st16 = (uint16_t *)wst;
-    uint8_t *sb = (uint8_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
-    uint32_t ob = 2u * o;   // byte offset of the slot
+    uint32_t ob = lds_addr(wst) + 2u * o;   // LDS address of the slot
     uint32_t bad = 0, h0e = 0, h0o = 0, l0e = 0, l0o = 0, h1e = 0, h1o = 0, L = 0, F = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -712,8 +715,8 @@ __device__ __forceinline__ bool scatter_quad(const LaneBytes &t, int r, uint32_t
         const uint32_t step = (lead >> 6) + (f0 >> 6);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            *(uint16_t *)(sb + ob) = (uint16_t)word_at2(he, ho, (uint32_t)k);
-            *(uint16_t *)(sb + ob + 2) = (uint16_t)word_at2(le, lo, (uint32_t)k);
+            *lptr<uint16_t>(ob) = (uint16_t)word_at2(he, ho, (uint32_t)k);
+            *lptr<uint16_t>(ob + 2) = (uint16_t)word_at2(le, lo, (uint32_t)k);
             ob = add_byte(ob, step, k);
         }
     }
@@ -748,10 +751,9 @@ template <uint32_t kClass, bool kFull>
 __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
                                                long long head, long long end, uint32_t lane) {
     uint16_t *st16 = (uint16_t *)wst;
-    uint8_t *sb = (uint8_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
-    uint32_t ob = 2u * o;   // byte offset of the slot
+    uint32_t ob = lds_addr(wst) + 2u * o;   // LDS address of the slot
     uint32_t bad = 0, ce0 = 0, co0 = 0, lead0 = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -768,7 +770,7 @@ __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_
         const uint32_t step = lead >> 6;   // per byte position: 2 past a leading byte
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            *(uint16_t *)(sb + ob) = (uint16_t)word_at2(ce, co, (uint32_t)k);
+            *lptr<uint16_t>(ob) = (uint16_t)word_at2(ce, co, (uint32_t)k);
             ob = add_byte(ob, step, k);
         }
     }
