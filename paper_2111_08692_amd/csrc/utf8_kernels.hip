@@ -152,11 +152,20 @@ __device__ __forceinline__ void finish_span(long long head, long long end, long 
 }
 
 // Continuation bits of dword k of row r, with positions outside the input
-// marked as continuations (so they neither emit words nor count).
+// marked as continuations (so they neither emit words nor count).  kEdge:
+// whether the wave reaches outside the input (t.edge) is known at compile
+// time (kInner, kEdgeWave) or tested per dword (kAnyWave).  The scatter
+// steps of single-buffer calls are compiled for inner and edge waves
+// apart, so the inner waves' code holds no branch per dword; the survey and
+// the batched calls test it (compiled twice, they need more registers than
+// the kernels have to spare).
+enum : int { kInner = 0, kEdgeWave = 1, kAnyWave = 2 };
+template <int kEdge>
 __device__ __forceinline__ uint32_t lane_cont_bits(const LaneBytes &t, int r, int k, long long wbase,
                                                    long long head, long long end, uint32_t lane) {
     uint32_t cb = cont_bits(t.d[r][k]);
-    if (t.edge) cb |= outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end);
+    if (kEdge == kEdgeWave || (kEdge == kAnyWave && t.edge))
+        cb |= outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end);
     return cb;
 }
 
@@ -228,7 +237,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
             const uint32_t f0 = e0 & (x << 3);
             const uint32_t m1 = __builtin_amdgcn_alignbyte(c0, pc0, 3), m2 = __builtin_amdgcn_alignbyte(e0, pe0, 2),
                            m3 = __builtin_amdgcn_alignbyte(f0, pf0, 1);
-            const uint32_t cb = lane_cont_bits(t, r, k, wbase, head, end, lane);
+            const uint32_t cb = lane_cont_bits<kAnyWave>(t, r, k, wbase, head, end, lane);
             if (kBatch) {
                 const uint32_t s0 = spread4(sbr >> (16 + 4 * k));     // start at t
                 const uint32_t s1 = __builtin_amdgcn_alignbyte(s0, ps, 3);  // start at t-1
@@ -314,9 +323,9 @@ __device__ __noinline__ u64 tile_width16(const uint8_t *frame, long long head, l
 // kFull (batched calls): an invalid string can end in the lane's first
 // dword and a valid one start later in the chunk, so the first leading
 // byte is looked for in the whole chunk.
-template <uint32_t kClass, bool kFull>
-__device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t gof, uint32_t *wst, long long wbase,
-                                            long long head, long long end, uint32_t lane) {
+template <uint32_t kClass, bool kFull, int kEdge>
+__device__ __forceinline__ void scatter_row_at(const LaneBytes &t, int r, uint32_t gof, uint32_t *wst, long long wbase,
+                                               long long head, long long end, uint32_t lane) {
     uint8_t *sb = (uint8_t *)wst;
     constexpr uint32_t kLast = 4u * (kStageSlots - 2);   // invalid input may announce more slots
     const uint32_t base = lds_addr(wst), last = base + kLast;
@@ -327,7 +336,7 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
     for (int j = 0; j < 4; ++j) {
         const uint32_t x = t.d[r][j];
         const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
-        const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+        const uint32_t lead = ~lane_cont_bits<kEdge>(t, r, j, wbase, head, end, lane) & 0x80808080u;
         if (j == 0) lead0 = lead;
         const uint32_t f0 = has4(kClass) ? ge_f0(x) & 0x80808080u : 0u;
         // per byte position: 4 (one slot) past a leading byte and 4 more
@@ -348,7 +357,7 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
     // rewrite the first slot
     uint32_t win = 0;
     bool has = false;
-    if (!kFull && !t.edge) {
+    if (!kFull && (kEdge == kInner || (kEdge == kAnyWave && !t.edge))) {
         has = lead0 != 0;
         const uint32_t p = (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3;   // first leading byte
         win = __builtin_amdgcn_alignbyte(t.d[r][1], t.d[r][0], p);
@@ -356,7 +365,7 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
         uint32_t p = 16;
 #pragma unroll
         for (int j = 3; j >= 0; --j) {
-            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+            const uint32_t lead = ~lane_cont_bits<kEdge>(t, r, j, wbase, head, end, lane) & 0x80808080u;
             if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
         }
         has = p < 16;
@@ -372,6 +381,16 @@ __device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t 
         const uint32_t a = has4(kClass) ? min(4u * gof, kLast) : 4u * gof;
         *(uint32_t *)(sb + a) = win;
     }
+}
+template <uint32_t kClass, bool kFull>
+__device__ __forceinline__ void scatter_row(const LaneBytes &t, int r, uint32_t gof, uint32_t *wst, long long wbase,
+                                            long long head, long long end, uint32_t lane) {
+    if (kFull)
+        scatter_row_at<kClass, kFull, kAnyWave>(t, r, gof, wst, wbase, head, end, lane);
+    else if (t.edge)
+        scatter_row_at<kClass, kFull, kEdgeWave>(t, r, gof, wst, wbase, head, end, lane);
+    else
+        scatter_row_at<kClass, kFull, kInner>(t, r, gof, wst, wbase, head, end, lane);
 }
 
 // ------------------------------------------------------------------------
@@ -747,9 +766,9 @@ __device__ __forceinline__ uint32_t class_words(uint32_t x, uint32_t nx, uint32_
 
 // Stage the lane's chunk of row r: words at halfword o + slot.  Returns
 // whether a value rule failed.  kFull as for scatter_row.
-template <uint32_t kClass, bool kFull>
-__device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
-                                               long long head, long long end, uint32_t lane) {
+template <uint32_t kClass, bool kFull, int kEdge>
+__device__ __forceinline__ bool scatter_words_at(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
+                                                  long long head, long long end, uint32_t lane) {
     uint16_t *st16 = (uint16_t *)wst;
     const uint32_t nx_row = next_dword(t, r, lane);
     const uint32_t o0 = o;
@@ -759,7 +778,7 @@ __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_
     for (int j = 0; j < 4; ++j) {
         const uint32_t x = t.d[r][j];
         const uint32_t nx = j < 3 ? t.d[r][j + 1] : nx_row;
-        const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+        const uint32_t lead = ~lane_cont_bits<kEdge>(t, r, j, wbase, head, end, lane) & 0x80808080u;
         uint32_t ce, co;
         bad |= class_words<kClass>(x, nx, ce, co);
         if (j == 0) {
@@ -777,14 +796,14 @@ __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_
     // rewrite the first slot (see scatter_row)
     uint32_t v = 0;
     bool has;
-    if (!kFull && !t.edge) {
+    if (!kFull && (kEdge == kInner || (kEdge == kAnyWave && !t.edge))) {
         has = lead0 != 0;
         v = word_at2(ce0, co0, (uint32_t)__builtin_ctz(lead0 | 0x80000000u) >> 3);
     } else {
         uint32_t p = 16;
 #pragma unroll
         for (int j = 3; j >= 0; --j) {
-            const uint32_t lead = ~lane_cont_bits(t, r, j, wbase, head, end, lane) & 0x80808080u;
+            const uint32_t lead = ~lane_cont_bits<kEdge>(t, r, j, wbase, head, end, lane) & 0x80808080u;
             if (lead) p = 4 * j + ((uint32_t)__builtin_ctz(lead) >> 3);
         }
         has = p < 16;
@@ -798,6 +817,13 @@ __device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_
     }
     if (has) st16[o0] = (uint16_t)v;
     return bad != 0;
+}
+template <uint32_t kClass, bool kFull>
+__device__ __forceinline__ bool scatter_words(const LaneBytes &t, int r, uint32_t o, uint32_t *wst, long long wbase,
+                                               long long head, long long end, uint32_t lane) {
+    if (kFull) return scatter_words_at<kClass, kFull, kAnyWave>(t, r, o, wst, wbase, head, end, lane);
+    return t.edge ? scatter_words_at<kClass, kFull, kEdgeWave>(t, r, o, wst, wbase, head, end, lane)
+                  : scatter_words_at<kClass, kFull, kInner>(t, r, o, wst, wbase, head, end, lane);
 }
 
 // Words of a wave's leading bytes stored one by one at their slots (`slot`:
