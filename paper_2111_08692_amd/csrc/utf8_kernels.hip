@@ -237,7 +237,8 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
             const uint32_t f0 = e0 & (x << 3);
             const uint32_t m1 = __builtin_amdgcn_alignbyte(c0, pc0, 3), m2 = __builtin_amdgcn_alignbyte(e0, pe0, 2),
                            m3 = __builtin_amdgcn_alignbyte(f0, pf0, 1);
-            const uint32_t cb = lane_cont_bits<kAnyWave>(t, r, k, wbase, head, end, lane);
+            // batched calls: positions outside the input are taken off below
+            const uint32_t cb = kBatch ? cont_bits(x) : lane_cont_bits<kAnyWave>(t, r, k, wbase, head, end, lane);
             if (kBatch) {
                 const uint32_t s0 = spread4(sbr >> (16 + 4 * k));     // start at t
                 const uint32_t s1 = __builtin_amdgcn_alignbyte(s0, ps, 3);  // start at t-1
@@ -260,6 +261,18 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
         }
         sv.width[r] = w;
     }
+    // batched calls, a wave at an end of the input: its positions outside
+    // the input hold zero bytes (not continuations), which the rows above
+    // counted as characters of one word; they emit nothing.  (Taken off
+    // here rather than per dword, the batched kernel spills 5 VGPRs instead
+    // of 16; the single-buffer kernel, which does not spill with the test per
+    // dword, would spill 5.)
+    if (kBatch && t.edge)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                sv.width[r] -= __popc(outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end));
     sv.mis = mis != 0;
     if (__ballot((aF0 & 0x80808080u) != 0))
         sv.cls = __ballot((aMid & 0x80808080u) != 0) ? kAny : kQuad;
