@@ -472,6 +472,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer three times (a plain copy kernel of known size, "
                          "the reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched 100 000-string leg, print its figures and exit (for profiled runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -490,6 +492,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
+        return
+
+    if args.batch_only:
+        import torch
+        import paper_2111_08692_amd as G
+        G.load()
+        aux = {}
+        batch_leg(G, torch.device("cuda:0"), torch.cuda.current_stream(), aux)
+        print(json.dumps(aux), flush=True)
         return
 
     size = args.size_mib << 20

@@ -151,14 +151,22 @@ __device__ __forceinline__ void finish_span(long long head, long long end, long 
     }
 }
 
+// Positions of the 16-byte chunk at frame position q0 that lie outside
+// [head, end).
+__device__ __forceinline__ uint32_t outside_count16(long long q0, long long head, long long end) {
+    const long long a = q0 < head ? head : q0;
+    const long long b = q0 + 16 > end ? end : q0 + 16;
+    return (uint32_t)(16 - (b > a ? b - a : 0));
+}
+
 // Continuation bits of dword k of row r, with positions outside the input
 // marked as continuations (so they neither emit words nor count).  kEdge:
 // whether the wave reaches outside the input (t.edge) is known at compile
 // time (kInner, kEdgeWave) or tested per dword (kAnyWave).  The scatter
 // steps of single-buffer calls are compiled for inner and edge waves
-// apart, so the inner waves' code holds no branch per dword; the survey and
-// the batched calls test it (compiled twice, they need more registers than
-// the kernels have to spare).
+// apart, so the inner waves' code holds no branch per dword; the batched
+// calls test it (compiled twice, they need more registers than the kernel
+// has to spare).  The survey needs no such test (see survey_span).
 enum : int { kInner = 0, kEdgeWave = 1, kAnyWave = 2 };
 template <int kEdge>
 __device__ __forceinline__ uint32_t lane_cont_bits(const LaneBytes &t, int r, int k, long long wbase,
@@ -237,8 +245,7 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
             const uint32_t f0 = e0 & (x << 3);
             const uint32_t m1 = __builtin_amdgcn_alignbyte(c0, pc0, 3), m2 = __builtin_amdgcn_alignbyte(e0, pe0, 2),
                            m3 = __builtin_amdgcn_alignbyte(f0, pf0, 1);
-            // batched calls: positions outside the input are taken off below
-            const uint32_t cb = kBatch ? cont_bits(x) : lane_cont_bits<kAnyWave>(t, r, k, wbase, head, end, lane);
+            const uint32_t cb = cont_bits(x);   // positions outside the input: below
             if (kBatch) {
                 const uint32_t s0 = spread4(sbr >> (16 + 4 * k));     // start at t
                 const uint32_t s1 = __builtin_amdgcn_alignbyte(s0, ps, 3);  // start at t-1
@@ -261,18 +268,12 @@ __device__ __forceinline__ void survey_span(const LaneBytes &t, long long wbase,
         }
         sv.width[r] = w;
     }
-    // batched calls, a wave at an end of the input: its positions outside
-    // the input hold zero bytes (not continuations), which the rows above
-    // counted as characters of one word; they emit nothing.  (Taken off
-    // here rather than per dword, the batched kernel spills 5 VGPRs instead
-    // of 16; the single-buffer kernel, which does not spill with the test per
-    // dword, would spill 5.)
-    if (kBatch && t.edge)
+    // a wave at an end of the input: its positions outside the input hold
+    // zero bytes (not continuations), which the rows above counted as
+    // characters of one word; they emit nothing
+    if (t.edge)
 #pragma unroll
-        for (int r = 0; r < kRows; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                sv.width[r] -= __popc(outside_bits(wbase + r * kRowBytes + 16 * (long long)lane + 4 * k, head, end));
+        for (int r = 0; r < kRows; ++r) sv.width[r] -= outside_count16(wbase + r * kRowBytes + 16 * (long long)lane, head, end);
     sv.mis = mis != 0;
     if (__ballot((aF0 & 0x80808080u) != 0))
         sv.cls = __ballot((aMid & 0x80808080u) != 0) ? kAny : kQuad;
