@@ -587,3 +587,26 @@ def test_span_owners_without_search():
             p = min(max(w * span - head, 0), n - 1)
             want.append(_owner_by_search(offsets, p))
         assert _owners_by_strings(offsets, head, span, nspans) == want, (offsets, head, span)
+
+
+def test_edge_width_correction():
+    """Waves at the ends of the input: the bytes outside [head, end) are
+    zeroed before the survey, so counting a chunk's output words over all 16
+    positions (one per non-continuation byte, one more per byte >= F0) and
+    then taking off the positions outside the input, in closed form
+    (16 - |[q0, q0 + 16) & [head, end)|), gives the count over the chunk's
+    own positions: a zero byte is neither a continuation nor >= F0."""
+    rng = np.random.default_rng(21)
+    for _ in range(4000):
+        head = int(rng.integers(0, 48))
+        end = head + int(rng.integers(0, 96))
+        q0 = 16 * int(rng.integers(-2, 10))
+        raw = rng.integers(0, 256, size=16)
+        inside = [head <= q0 + i < end for i in range(16)]
+        b = [int(x) if ins else 0 for x, ins in zip(raw, inside)]
+        own = sum((1 + (x >= 0xF0)) for x, ins in zip(b, inside) if ins and (x & 0xC0) != 0x80)
+        every = sum((1 + (x >= 0xF0)) for x in b if (x & 0xC0) != 0x80)
+        a, z = max(q0, head), min(q0 + 16, end)
+        outside = 16 - (z - a if z > a else 0)
+        assert outside == sum(not ins for ins in inside)
+        assert every - outside == own
