@@ -671,9 +671,13 @@ __device__ __forceinline__ void words4_half(uint32_t x, uint32_t y, uint32_t z, 
     const uint32_t sel = sconst<kSel>();
     const uint32_t a = __builtin_amdgcn_perm(0u, x, sel), b = __builtin_amdgcn_perm(0u, y, sel),
                    c = __builtin_amdgcn_perm(0u, z, sel), d = __builtin_amdgcn_perm(0u, w, sel);
-    const uint32_t hi = as_u32(as_h2(a) * (unsigned short)256 + as_h2(b) * (unsigned short)4 +
-                               (as_h2(c) >> (unsigned short)4) + (unsigned short)0xE5B8);
-    lw = as_u32(as_h2(c & 0x000F000Fu) * (unsigned short)64 + as_h2(d) + (unsigned short)0xDB80);
+    // multipliers from scalar registers: multiply-adds (v_pk_mad_u16) rather
+    // than shifts and adds
+    const u16x2 m256 = as_h2(sconst<0x01000100u>()), m4 = as_h2(sconst<0x00040004u>()),
+                m64 = as_h2(sconst<0x00400040u>());
+    const uint32_t hi = as_u32((as_h2(b) * m4 + (as_h2(a) * m256 + (as_h2(c) >> (unsigned short)4))) +
+                               (unsigned short)0xE5B8);
+    lw = as_u32((as_h2(c & 0x000F000Fu) * m64 + as_h2(d)) + (unsigned short)0xDB80);
     const uint32_t m = __builtin_amdgcn_perm(0u, mf, sconst<kMaskSel>());
     hw = (m & hi) | (~m & a);   // the byte itself at the other positions
 }
