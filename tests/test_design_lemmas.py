@@ -610,3 +610,96 @@ def test_edge_width_correction():
         outside = 16 - (z - a if z > a else 0)
         assert outside == sum(not ins for ins in inside)
         assert every - outside == own
+
+
+# 6. Row write-out with carried blocks.  A wave stages each row's output
+#    [g0, g1) by 16-byte blocks of global memory (byte g at stage byte
+#    g - (g0 & ~15)) and stores it: lane i takes blocks i, i + 64, ... up to
+#    the row's last whole block; the row's unfinished last block is carried
+#    to the next row, whose block 0 it completes (in registers); a block
+#    that begins before the wave's first byte `wstart` is stored in part
+#    with aligned stores of 1..8 bytes (never below the unit size); after
+#    a row cut short (the next row starts further on) and at the wave's end
+#    the carried block is stored in part.  Every byte of every row must be
+#    written once with its value; the gap after a row cut short (which only
+#    happens past an error, where the output is unspecified) may be written
+#    once with any value; nothing else is written.
+
+def store_part(mem, c, a, b, block, unit):
+    for sz in (1, 2, 4, 8):   # up to the first 16-byte aligned chunk
+        if sz >= unit and (a & sz) and a + sz <= b:
+            for j in range(sz):
+                mem.append((a + j, block[a - c + j], sz, a))
+            a += sz
+    for sz in (8, 4, 2, 1):   # the rest, largest first
+        if sz >= unit and a + sz <= b:
+            for j in range(sz):
+                mem.append((a + j, block[a - c + j], sz, a))
+            a += sz
+    assert a == b, (c, a, b)
+
+
+def write_row_model(mem, g0, g1, wstart, stage, carry, merge, unit):
+    c0 = g0 & ~15
+    lo = max(c0, wstart)
+    hi = g1 & ~15
+    k = g0 & 15
+    merge = merge and k != 0
+    nb = (hi - c0) >> 4
+    part0 = c0 < lo
+    for b in range(nb):
+        block = list(stage[16 * b:16 * b + 16])
+        if b == 0 and merge:
+            block[:k] = carry[:k]
+        if b == 0 and part0:
+            store_part(mem, c0, lo, c0 + 16, block, unit)
+        else:
+            mem.extend((c0 + 16 * b + j, block[j], 16, c0 + 16 * b) for j in range(16))
+    if g1 & 15:
+        blk = list(stage[hi - c0:hi - c0 + 16])
+        if merge and nb == 0:
+            blk[:k] = carry[:k]
+        carry = blk
+    return carry
+
+
+@pytest.mark.parametrize("unit", [1, 2])
+def test_row_write_out_with_carry(unit):
+    rng = np.random.default_rng(31 + unit)
+    for trial in range(3000):
+        wstart = 4096 + unit * int(rng.integers(0, 64 // unit))
+        rows, u, gap = [], wstart, set()
+        for _ in range(int(rng.integers(1, 6))):
+            if rng.random() < 0.15:   # a row cut short before: the next one starts further on
+                g = unit * int(rng.integers(1, 40))
+                gap.update(range(u, u + g))
+                u += g
+            n = unit * int(rng.choice([0, 1, 2, 3, 7, 8, 9, 15, 16, 17, 100, 1000, 1032]))
+            rows.append((u, u + n))
+            u += n
+        want = {}
+        mem, carry, wlo, gend = [], [0] * 16, wstart, wstart
+        for g0, g1 in rows:
+            value = lambda a: (a * 131 + trial) & 0xFF
+            stage = [int(x) for x in rng.integers(0, 256, size=16 * ((g1 - (g0 & ~15)) // 16 + 2))]
+            for a in range(g0, g1):
+                stage[a - (g0 & ~15)] = value(a)
+                want[a] = value(a)
+            if g0 < g1 and gend != g0:
+                if gend & 15:
+                    c = gend & ~15
+                    store_part(mem, c, max(c, wlo), gend, carry, unit)
+                wlo = gend
+            if g0 < g1:
+                carry = write_row_model(mem, g0, g1, wlo, stage, carry, gend == g0 and gend > wlo, unit)
+                gend = g1
+        if gend & 15:
+            c = gend & ~15
+            store_part(mem, c, max(c, wlo), gend, carry, unit)
+        got = {}
+        for a, v, sz, base in mem:
+            assert base % sz == 0 and sz >= unit, (trial, a, sz)
+            assert a not in got, (trial, a)    # each byte once
+            got[a] = v
+        assert {a: v for a, v in got.items() if a not in gap} == want, trial
+        assert all(a < gend for a in got if a in gap), trial
