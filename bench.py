@@ -474,6 +474,8 @@ def main():
                          "the reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched 100 000-string leg, print its figures and exit (for profiled runs)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving leg, print its figures and exit (for profiled runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -501,6 +503,20 @@ def main():
         aux = {}
         batch_leg(G, torch.device("cuda:0"), torch.cuda.current_stream(), aux)
         print(json.dumps(aux), flush=True)
+        return
+
+    if args.serve_only:
+        from workloads import make_requests
+        ex = ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("fork"))
+        small = make_buffer("mix1m", 1 << 20, SEED_MIX1M)
+        reqs = make_requests(SERVE_REQUESTS, executor=ex)
+        ex.shutdown()
+        import paper_2111_08692_amd as G
+        G.load()
+        aux = {}
+        serve_leg(reqs, small, aux)
+        print(json.dumps(aux), flush=True)
+        reap_children()
         return
 
     size = args.size_mib << 20
